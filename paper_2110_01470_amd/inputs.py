@@ -1,0 +1,71 @@
+"""Seeded synthetic workloads.
+
+This module only draws objective instances and names workloads; it holds none
+of the optimiser's arithmetic.  The CPU oracle and the GPU library are both
+fed from it, so the two sides see the same FP32 arrays.
+
+The paper's benchmarks are closed-form functions (Table 3.2) on D=50 with
+N=100..350 particles and 1000 iterations (Sec. 3.4.2).  The workloads below
+keep that form -- a shifted optimum inside a box -- at the sizes the GPU path
+is built for.  Instances come from numpy's PCG64 with the workload's seed:
+the shift s ~ U[s_lo, s_hi], the ripple weights w = 10**(3 U[0,1]) (log-uniform
+on [1, 1e3]) and the dense matrix A_kj ~ N(0,1)/sqrt(D), each rounded once to
+FP32.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+KINDS = ("sphere", "ripple", "dense")
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    kind: str          # "sphere" | "ripple" | "dense"
+    n: int             # particles (Nsol)
+    d: int             # variables per particle (Nvar)
+    lo: float          # box [varMin, varMax]
+    hi: float
+    cg: float
+    cp: float
+    cw: float
+    generations: int   # update generations after initialisation
+    seed: int          # objective instance seed and Philox key
+    s_lo: float        # shift range
+    s_hi: float
+
+    def objective(self):
+        return make_objective(self.kind, self.d, self.seed, self.s_lo, self.s_hi)
+
+    def scaled(self, **changes) -> "Workload":
+        return dataclasses.replace(self, **changes)
+
+
+WORKLOADS = {
+    w.name: w
+    for w in (
+        Workload("sphere_n100_d30", "sphere", 100, 30, -100.0, 100.0, 0.4, 0.7, 0.9,
+                 1000, 1, -50.0, 50.0),
+        Workload("ripple_n65536_d1000", "ripple", 65536, 1000, -100.0, 100.0, 0.4, 0.7, 0.9,
+                 1000, 2, -50.0, 50.0),
+        Workload("dense_n16384_d256", "dense", 16384, 256, -10.0, 10.0, 0.4, 0.7, 0.9,
+                 2000, 3, -5.0, 5.0),
+    )
+}
+
+
+def make_objective(kind: str, d: int, seed: int, s_lo: float, s_hi: float):
+    """(s, w, a) as FP32 arrays; w is None unless ripple, a is None unless dense."""
+    if kind not in KINDS:
+        raise ValueError(f"unknown objective kind {kind!r}")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = rng.uniform(s_lo, s_hi, size=d).astype(np.float32)
+    w = a = None
+    if kind == "ripple":
+        w = (10.0 ** (3.0 * rng.uniform(0.0, 1.0, size=d))).astype(np.float32)
+    elif kind == "dense":
+        a = (rng.standard_normal((d, d)) / np.sqrt(d)).astype(np.float32)
+    return s, w, a
