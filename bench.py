@@ -1,0 +1,185 @@
+"""Throughput of the SSO generation on one MI355X.
+
+A step is one generation of Algorithm 2 over the whole swarm (Eq. 2.1 select,
+fitness, pBest update, gBest argmin) -- one launch of the fused generation
+kernel.  The default workload is the large ripple swarm (N=65536 particles,
+D=1000 FP32 variables, 1000 generations).  Timing: W warm-up generations on
+a throw-away swarm, then a fresh swarm is initialised (untimed, state already
+resident in HBM) and exactly K generations 1..K are timed with HIP events on
+the stream the kernels run on.
+
+Prints one JSON line:
+  value    = N * D * K / seconds  (particle-variable updates per second,
+             fitness included)
+  roofline = 12 algorithmic bytes per update (read x, read p, write x')
+             / mean generation time, against 8 TB/s HBM3E (dense objective:
+             2 N D^2 FLOP per generation against 157.3 TFLOP/s FP32 matrix)
+  cpu_baseline = the CPU oracle, single-threaded, on a few generations of the
+             same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_MATRIX_PEAK_TFLOPS = 157.3
+BYTES_PER_UPDATE = 12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ("sso_device.hpp", "sso_layout.hpp", "gen_stream.hip", "gen_dense.hip",
+                  "resident.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2110_01470_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, per_launch_units):
+    """HBM bytes per launch from the committed counter summary, or None if the
+    kernels changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_gpu(wl, steps, warmup, engine):
+    import torch
+
+    from paper_2110_01470_amd.binding import Swarm
+
+    s, w, a = wl.objective()
+    stream = torch.cuda.Stream()
+    args = (wl.n, wl.d, wl.kind, wl.lo, wl.hi, wl.cg, wl.cp, wl.cw, wl.seed, s, w, a)
+    if warmup:
+        warm = Swarm(*args, engine=engine, stream=stream)
+        warm.run(warmup)
+        stream.synchronize()
+        warm.close()
+        del warm
+    sw = Swarm(*args, engine=engine, stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    sw.run(steps)
+    stop.record(stream)
+    stop.synchronize()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    g, fg, gidx, gen = sw.best()
+    return ms, fg, gen
+
+
+def time_oracle(wl, gens):
+    import oracle
+
+    kind = {"sphere": oracle.SPHERE, "ripple": oracle.RIPPLE, "dense": oracle.DENSE}[wl.kind]
+    s, w, a = wl.objective()
+    orc = oracle.Swarm(wl.n, wl.d, kind, wl.lo, wl.hi, wl.cg, wl.cp, wl.cw, wl.seed, s, w, a)
+    orc.init()
+    t0 = time.perf_counter()
+    orc.run(gens)
+    return time.perf_counter() - t0
+
+
+def main():
+    from paper_2110_01470_amd.inputs import WORKLOADS
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed generations (default: the workload's)")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="ripple_n65536_d1000", choices=sorted(WORKLOADS))
+    ap.add_argument("--engine", default="auto", choices=["auto", "stream", "resident"])
+    ap.add_argument("--cpu-gens", type=int, default=None,
+                    help="oracle generations for cpu_baseline (0 = skip)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the swarm of one GPU is the unit; see the sharding notes in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    wl = WORKLOADS[args.workload]
+    steps = args.steps if args.steps is not None else wl.generations
+    log(f"workload {wl.name}: N={wl.n} D={wl.d} steps={steps} warmup={args.warmup}")
+    ms, fg, gen = time_gpu(wl, steps, args.warmup, args.engine)
+    sec = ms / 1e3
+    updates = wl.n * wl.d * steps
+    value = updates / sec
+    ms_per_step = ms / steps
+    log(f"gpu: {ms:.3f} ms for {steps} generations, fG={fg:.6g} at t={gen}")
+
+    if wl.kind == "dense":
+        flop = 2.0 * wl.n * wl.d * wl.d
+        achieved = flop / (ms_per_step / 1e3) / 1e12
+        roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MATRIX_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / FP32_MATRIX_PEAK_TFLOPS,
+                    "traffic": measured_traffic(wl.name, 1)}
+    else:
+        byt = BYTES_PER_UPDATE * wl.n * wl.d
+        achieved = byt / (ms_per_step / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl.name, 1)}
+
+    cpu_gens = args.cpu_gens
+    if cpu_gens is None:
+        # About 10-30 s of single-threaded oracle work.
+        cpu_gens = max(1, min(steps, int(4 * 65536 * 1000 // (wl.n * wl.d)) or 1))
+        if wl.kind == "dense":
+            cpu_gens = max(1, min(steps, 4 * 16384 * 256 // (wl.n * wl.d)))
+    cpu = None
+    if cpu_gens > 0:
+        csec = time_oracle(wl, cpu_gens)
+        cpu = {"value": wl.n * wl.d * cpu_gens / csec, "unit": "particle-var updates/s",
+               "cores": 1, "kind": "oracle",
+               "sample": f"{cpu_gens} generations of {wl.name} after initialisation, "
+                         f"single-threaded FP64 oracle, {csec:.2f} s"}
+        log(f"cpu oracle: {csec:.2f} s for {cpu_gens} generations")
+
+    rec = {
+        "metric": "particle-var updates/s incl. fitness",
+        "value": value,
+        "unit": "particle-var updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "objective": wl.kind, "n": wl.n, "d": wl.d,
+                   "generations": steps, "engine": args.engine},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,151 @@
+/*
+ * sso.h -- C ABI of the MI355X Simplified Swarm Optimization library
+ * (libsso.so).  Method: Yeh, Liu, Tan, Huang, "Implementation of Parallel
+ * Simplified Swarm Optimization in CUDA", arXiv 2110.01470.
+ *
+ * The library runs the synchronous SSO flow of Algorithm 2 on one GPU: an
+ * initialisation (kernel (I), Sec. 2.3.1) followed by generations, each of
+ * which sets every variable of every particle by Eq. (2.1), evaluates every
+ * particle, replaces pBests that improved (Algorithm 3) and takes gBest as
+ * the pBest of lowest fitness (Algorithm 4).  The problem statement follows
+ * Sec. 3.3: f(X) over the box [L, U]^Nvar with Nsol particles; the variables
+ * of Table 3.1 map onto sso_config below.
+ *
+ * Conventions for every call:
+ *   - Plain C types only; no exceptions cross the boundary.
+ *   - Host arrays belong to the caller and are read or written during the
+ *     call only.  The device workspace belongs to the caller (any device
+ *     allocation of at least sso_workspace_bytes() bytes, 256-byte aligned)
+ *     and must outlive the context.  The context belongs to the library and
+ *     is freed by sso_destroy().
+ *   - sso_init/sso_step/sso_run/sso_debug_rng only enqueue work on the
+ *     caller's HIP stream and return; sso_get_* and sso_set_state synchronise
+ *     that stream.
+ *   - One host thread at a time may drive a context.
+ *   - Return value: SSO_OK or a negative SSO_E_* code; sso_last_error()
+ *     gives the detail (including the HIP error string for SSO_E_HIP).
+ */
+#ifndef SSO_H
+#define SSO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSO_OK             0
+#define SSO_E_INVAL       -1 /* bad argument or configuration                  */
+#define SSO_E_NOMEM       -2 /* workspace smaller than sso_workspace_bytes()   */
+#define SSO_E_HIP         -3 /* a HIP runtime call failed                      */
+#define SSO_E_UNSUPPORTED -4 /* size beyond a kernel limit, or not a gfx950 GPU */
+#define SSO_E_STATE       -5 /* call out of order (e.g. trace already dropped)  */
+
+/* Objectives (all minimised; optimum 0 at x = s). */
+typedef enum {
+    SSO_OBJ_SPHERE = 0, /* sum_j (x_j - s_j)^2                                  */
+    SSO_OBJ_RIPPLE = 1, /* sum_j w_j (x_j - s_j)^2 + 0.5 sum_j sin^2(3(x_j - s_j)) */
+    SSO_OBJ_DENSE  = 2  /* || A (x - s) ||^2, A is d x d                        */
+} sso_objective;
+
+/* Order of the four intervals of Eq. (2.1).  A uniform word k in [0, 2^32)
+ * stands for rand() = k 2^-32, and each threshold c becomes ceil(c 2^32).
+ *   SSO_ORDER_GPS : gBest [0,cg), pBest [cg,cp), self [cp,cw), fresh [cw,1);
+ *                   needs cg <= cp <= cw.
+ *   SSO_ORDER_EQ21: self [0,cw), pBest [cw,cp), gBest [cp,cg), fresh [cg,1),
+ *                   the order Eq. (2.1) prints; needs cw <= cp <= cg.
+ * The fresh value is uniform on [lo, hi] (Table 3.1, "range for rand() > Cg"). */
+typedef enum { SSO_ORDER_GPS = 0, SSO_ORDER_EQ21 = 1 } sso_order;
+
+/* Engines.  AUTO picks RESIDENT when the whole swarm fits one workgroup's
+ * registers, else STREAM.  Every engine gives bit-identical positions. */
+typedef enum {
+    SSO_ENGINE_AUTO     = 0,
+    SSO_ENGINE_STREAM   = 1, /* one fused kernel per generation                 */
+    SSO_ENGINE_RESIDENT = 2  /* one workgroup keeps the swarm on chip and loops */
+} sso_engine;
+
+typedef struct {
+    uint32_t n;          /* Nsol, particles, >= 1, < 2^31                         */
+    uint32_t d;          /* Nvar, variables per particle, >= 1 (DENSE: <= 256)    */
+    float    lo, hi;     /* [varMin, varMax]; finite, lo < hi, hi - lo finite     */
+    double   cg, cp, cw; /* thresholds in [0,1], ordered as `order` requires, and
+                            the fresh interval must hold more than 2^24 words
+                            (1 - max threshold > 2^-8, checked in integer form)  */
+    uint64_t seed;       /* Philox key: (seed mod 2^32, seed div 2^32)            */
+    uint32_t swarm_id;   /* fourth Philox counter word                            */
+    int32_t  kind;       /* sso_objective                                         */
+    int32_t  order;      /* sso_order                                             */
+    int32_t  engine;     /* sso_engine                                            */
+    uint32_t lanes;      /* STREAM engine lanes per particle: 0 = auto, else a
+                            power of two in [8, 64]                               */
+    uint32_t trace_cap;  /* generations of (fG, gidx, improved) kept on device;
+                            0 = 4096, else >= 4                                   */
+    const float *s;      /* host [d]: shift (optimum)                             */
+    const float *w;      /* host [d]: RIPPLE weights, else ignored (may be NULL)  */
+    const float *a;      /* host [d*d] row-major: DENSE matrix, else ignored      */
+} sso_config;
+
+typedef struct sso_ctx sso_ctx;
+
+/* Bytes of device workspace the configuration needs; 0 if it is invalid. */
+size_t sso_workspace_bytes(const sso_config *cfg);
+
+/* Validates cfg, lays the state out in the workspace, uploads s, w, a
+ * (synchronously), and enqueues the initialisation on `hip_stream`
+ * (a hipStream_t; NULL = the null stream): X^0 uniform on [lo, hi] from the
+ * Philox words of generation 0, P^0 = X^0, fP^0 = f(X^0), gBest^0 = the
+ * lowest-index argmin.  *out receives the context; on error *out is NULL. */
+int sso_init(const sso_config *cfg, void *dev_workspace, size_t workspace_bytes,
+             void *hip_stream, sso_ctx **out);
+
+/* Enqueue one generation t -> t + 1 (Algorithm 2's loop body). */
+int sso_step(sso_ctx *ctx);
+
+/* Enqueue `generations` generations. */
+int sso_run(sso_ctx *ctx, uint32_t generations);
+
+/* Synchronise, then copy gBest out: g_out host [d] (may be NULL), its FP32
+ * fitness, its particle index, and the number of generations done. */
+int sso_get_best(sso_ctx *ctx, float *g_out, float *f_out, uint32_t *idx_out,
+                 uint64_t *gen_out);
+
+/* Synchronise, then copy the state out into host arrays: x [n*d] current
+ * positions, p [n*d] pBests, fp [n] pBest fitness (FP32), *t generations
+ * done.  Any pointer may be NULL. */
+int sso_get_state(sso_ctx *ctx, float *x, float *p, float *fp, uint64_t *t);
+
+/* Replace the state with host arrays x, p [n*d], fp [n] and the generation
+ * count t; gBest becomes the lowest-index argmin of fp.  Used for
+ * checkpoint/resume and for parity checks from a given state.  Synchronises. */
+int sso_set_state(sso_ctx *ctx, const float *x, const float *p, const float *fp,
+                  uint64_t t);
+
+/* Synchronise, then copy the per-generation trace of generations
+ * [first, first + count): fG (FP32 gBest fitness), gBest index, and the number
+ * of pBests replaced in that generation (n for the initialisation).  The
+ * device keeps the last trace_cap - 2 generations; asking for older or
+ * future ones returns SSO_E_STATE.  Any output pointer may be NULL. */
+int sso_get_trace(sso_ctx *ctx, uint64_t first, uint32_t count, float *fg,
+                  uint32_t *gidx, uint32_t *improved);
+
+/* Enqueue: write the Philox word of every (particle i, variable j) for
+ * generation t to dev_words[i*d + j] (device memory, n*d uint32), with the
+ * same generator and counter layout the kernels use. */
+int sso_debug_rng(sso_ctx *ctx, uint64_t t, uint32_t *dev_words);
+
+/* Free the context (not the workspace).  NULL is allowed. */
+void sso_destroy(sso_ctx *ctx);
+
+/* Static text for an SSO_* code. */
+const char *sso_strerror(int code);
+
+/* Detail of the last error on ctx, or of the calling thread's last failed
+ * sso_init/sso_workspace_bytes when ctx is NULL.  Empty string if none. */
+const char *sso_last_error(const sso_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSO_H */

@@ -1,0 +1,206 @@
+"""ctypes binding of the C ABI in include/sso.h (libsso.so).
+
+Argument marshalling only: every step of the optimiser runs in the HIP
+kernels of libsso.so.  PyTorch supplies the device workspace (a uint8 tensor)
+and the HIP stream, nothing else.  There is no CPU fallback: if libsso.so is
+missing or no GPU is present, constructing a Swarm raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB_PATH
+
+OK, E_INVAL, E_NOMEM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5
+OBJ = {"sphere": 0, "ripple": 1, "dense": 2}
+ORDER_GPS, ORDER_EQ21 = 0, 1
+ENGINE = {"auto": 0, "stream": 1, "resident": 2}
+
+
+class SSOError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sso error {code}: {msg}")
+        self.code = code
+        self.msg = msg
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint32),
+        ("d", ctypes.c_uint32),
+        ("lo", ctypes.c_float),
+        ("hi", ctypes.c_float),
+        ("cg", ctypes.c_double),
+        ("cp", ctypes.c_double),
+        ("cw", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("swarm_id", ctypes.c_uint32),
+        ("kind", ctypes.c_int32),
+        ("order", ctypes.c_int32),
+        ("engine", ctypes.c_int32),
+        ("lanes", ctypes.c_uint32),
+        ("trace_cap", ctypes.c_uint32),
+        ("s", ctypes.c_void_p),
+        ("w", ctypes.c_void_p),
+        ("a", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libsso.so from the package directory; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+    cfgp = ctypes.POINTER(Config)
+    sig = {
+        "sso_workspace_bytes": (ctypes.c_size_t, [cfgp]),
+        "sso_init": (ctypes.c_int, [cfgp, P, ctypes.c_size_t, P, ctypes.POINTER(P)]),
+        "sso_step": (ctypes.c_int, [P]),
+        "sso_run": (ctypes.c_int, [P, u32]),
+        "sso_get_best": (ctypes.c_int, [P, P, P, P, P]),
+        "sso_get_state": (ctypes.c_int, [P, P, P, P, P]),
+        "sso_set_state": (ctypes.c_int, [P, P, P, P, u64]),
+        "sso_get_trace": (ctypes.c_int, [P, u64, u32, P, P, P]),
+        "sso_debug_rng": (ctypes.c_int, [P, u64, P]),
+        "sso_destroy": (None, [P]),
+        "sso_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "sso_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+
+
+def make_config(n, d, kind, lo, hi, cg, cp, cw, seed, s, w=None, a=None, swarm_id=0,
+                order=ORDER_GPS, engine="auto", lanes=0, trace_cap=0):
+    """Returns (Config, keepalive) with host arrays pinned in `keepalive`."""
+    s, w, a = _f32(s), _f32(w), _f32(a)
+    cfg = Config(n=n, d=d, lo=lo, hi=hi, cg=cg, cp=cp, cw=cw, seed=seed, swarm_id=swarm_id,
+                 kind=OBJ[kind] if isinstance(kind, str) else kind, order=order,
+                 engine=ENGINE[engine] if isinstance(engine, str) else engine, lanes=lanes,
+                 trace_cap=trace_cap, s=s.ctypes.data if s is not None else None,
+                 w=w.ctypes.data if w is not None else None,
+                 a=a.ctypes.data if a is not None else None)
+    return cfg, (s, w, a)
+
+
+def workspace_bytes(cfg):
+    lib = load()
+    nbytes = lib.sso_workspace_bytes(ctypes.byref(cfg))
+    if nbytes == 0:
+        raise SSOError(E_INVAL, lib.sso_last_error(None).decode())
+    return nbytes
+
+
+class Swarm:
+    """One swarm on one GPU.  Mirrors sso_init / sso_step / sso_run /
+    sso_get_best and the state, trace and RNG hooks."""
+
+    def __init__(self, n, d, kind, lo, hi, cg, cp, cw, seed, s, w=None, a=None, swarm_id=0,
+                 order=ORDER_GPS, engine="auto", lanes=0, trace_cap=0, device="cuda",
+                 stream=None):
+        import torch
+
+        self._lib = load()
+        self.n, self.d = n, d
+        self._cfg, self._keep = make_config(n, d, kind, lo, hi, cg, cp, cw, seed, s, w, a,
+                                            swarm_id, order, engine, lanes, trace_cap)
+        nbytes = workspace_bytes(self._cfg)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self._lib.sso_init(ctypes.byref(self._cfg), self.workspace.data_ptr(), nbytes,
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if rc != OK:
+            raise SSOError(rc, self._lib.sso_last_error(None).decode())
+        self._ctx = ctx
+
+    def _check(self, rc):
+        if rc != OK:
+            raise SSOError(rc, self._lib.sso_last_error(self._ctx).decode())
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.sso_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self):
+        self._check(self._lib.sso_step(self._ctx))
+        return self
+
+    def run(self, generations):
+        self._check(self._lib.sso_run(self._ctx, generations))
+        return self
+
+    def best(self):
+        """(g [d], fG, gidx, generations done)."""
+        g = np.zeros(self.d, np.float32)
+        f = ctypes.c_float()
+        idx = ctypes.c_uint32()
+        gen = ctypes.c_uint64()
+        self._check(self._lib.sso_get_best(self._ctx, _ptr(g), ctypes.byref(f), ctypes.byref(idx),
+                                           ctypes.byref(gen)))
+        return g, float(f.value), int(idx.value), int(gen.value)
+
+    def state(self):
+        """(x [n,d], p [n,d], fp [n], t)."""
+        x = np.zeros((self.n, self.d), np.float32)
+        p = np.zeros((self.n, self.d), np.float32)
+        fp = np.zeros(self.n, np.float32)
+        t = ctypes.c_uint64()
+        self._check(self._lib.sso_get_state(self._ctx, _ptr(x), _ptr(p), _ptr(fp),
+                                            ctypes.byref(t)))
+        return x, p, fp, int(t.value)
+
+    def set_state(self, x, p, fp, t):
+        x = _f32(x).reshape(self.n, self.d)
+        p = _f32(p).reshape(self.n, self.d)
+        fp = _f32(fp).reshape(self.n)
+        self._check(self._lib.sso_set_state(self._ctx, _ptr(x), _ptr(p), _ptr(fp), t))
+        return self
+
+    def trace(self, first, count):
+        """(fG [count], gidx [count], improved [count]) for generations first.."""
+        fg = np.zeros(count, np.float32)
+        gi = np.zeros(count, np.uint32)
+        im = np.zeros(count, np.uint32)
+        self._check(self._lib.sso_get_trace(self._ctx, first, count, _ptr(fg), _ptr(gi), _ptr(im)))
+        return fg, gi, im
+
+    def debug_rng(self, t):
+        """The device's Philox words of generation t, as an [n, d] uint32 array."""
+        import torch
+
+        out = torch.empty(self.n * self.d, dtype=torch.int32, device=self.device)
+        self._check(self._lib.sso_debug_rng(self._ctx, t, ctypes.c_void_p(out.data_ptr())))
+        self.stream.synchronize()
+        return out.cpu().numpy().view(np.uint32).reshape(self.n, self.d)

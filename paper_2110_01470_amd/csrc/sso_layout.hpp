@@ -1,0 +1,56 @@
+// State layout in device memory and the launchers each kernel file exports.
+//
+// Per particle i the workspace holds two rows of dp floats (dp = d rounded up
+// to 32, so every row starts on a 128-byte line) and a state word:
+//   bit 0 (ST_ROW)   which of the two rows holds the pBest,
+//   bit 1 (ST_ALIAS) the current position equals the pBest (the other row is
+//                    stale and is not read).
+// A generation reads pBest (and, unless aliased, X) and writes the new
+// position X' into the row that does NOT hold the pBest.  If X' improves on
+// the pBest the two roles swap (ST_ROW flips, ST_ALIAS set); otherwise
+// ST_ALIAS clears.  No pBest row is ever written in place during a
+// generation, so gBest of the previous generation -- row (key & 1) of
+// particle (key >> 1) -- stays valid while every particle reads it, and an
+// improved particle costs no extra copy: 12 bytes per variable at most
+// (read X, read P, write X'), 8 when aliased.
+#pragma once
+
+#include <stdint.h>
+
+namespace sso {
+
+enum { OBJ_SPHERE = 0, OBJ_RIPPLE = 1, OBJ_DENSE = 2 };
+enum : uint32_t { ST_ROW = 1u, ST_ALIAS = 2u };
+
+constexpr uint32_t kRowAlign = 32;      // floats per row alignment unit (128 B)
+constexpr uint32_t kDenseMaxD = 256;    // dense kernel limit on d
+
+struct SwarmDev {
+    float *rows;                 // [2][n][dp]
+    float *fp;                   // [n] pBest fitness (FP32)
+    uint32_t *st;                // [n] state word
+    const float *s;              // [dp] shift, zero padded
+    const float *w;              // [dp] ripple weights, zero padded (or null)
+    const float *a;              // dense matrix, layout of the dense kernel (or null)
+    unsigned long long *keys;    // [trace_cap] gBest key per generation (ring)
+    uint32_t *cnt;               // [trace_cap] improved pBests per generation (ring)
+    uint64_t buf;                // floats from row buffer 0 to row buffer 1 (n * dp)
+    uint32_t n, d, dp, chunks;   // chunks = ceil(d / 4)
+    uint32_t trace_cap;
+    uint32_t th0, th1, th2, r;   // integer thresholds and fresh-draw rescale
+    float lo, span;
+    uint32_t key0, key1, swarm;  // Philox key and fourth counter word
+    int32_t kind, order;
+};
+
+// Launchers (each returns hipSuccess or the launch error).
+int launch_stream_generation(const SwarmDev &S, uint32_t t, uint32_t lanes, void *stream);
+int launch_dense_generation(const SwarmDev &S, uint32_t t, void *stream);
+int launch_fill_trace(const SwarmDev &S, void *stream);
+int launch_debug_rng(const SwarmDev &S, uint32_t t, uint32_t *out, void *stream);
+int launch_resident(const SwarmDev &S, uint32_t t_first, uint32_t generations, void *stream);
+bool resident_fits(uint32_t n, uint32_t d, int kind);
+uint64_t dense_matrix_floats(uint32_t d);
+void dense_pack_matrix(const float *a, uint32_t d, float *out);
+
+}  // namespace sso

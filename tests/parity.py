@@ -1,0 +1,102 @@
+"""Helpers for comparing the GPU library with the CPU oracle.
+
+The bar:
+* positions X, pBests P and gBest g: bit-exact (they are FP32 values that are
+  only drawn or copied, never computed);
+* Philox words, branch choices and particle indices: bit-exact;
+* FP32 fitness against the oracle's FP64 value: relative error <= REL_TOL;
+* a pBest or gBest decision may differ from the oracle's only when the two
+  FP64 values it compares are within BAND of each other (both sides then hold
+  a correct FP32 decision); the test counts such events and re-synchronises
+  the GPU to the oracle's state, which is an input to the GPU, never the
+  other way round.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_2110_01470_amd.inputs import make_objective
+
+REL_TOL = 1e-5
+BAND = 2 * REL_TOL
+KIND = {"sphere": oracle.SPHERE, "ripple": oracle.RIPPLE, "dense": oracle.DENSE}
+
+
+def near(a, b, band=BAND):
+    return abs(a - b) <= band * max(abs(a), abs(b))
+
+
+class Pair:
+    """An oracle swarm and a GPU swarm built from the same seeded instance."""
+
+    def __init__(self, kind, n, d, lo=-100.0, hi=100.0, cg=0.4, cp=0.7, cw=0.9, seed=1,
+                 s_range=(-50.0, 50.0), order=oracle.ORDER_GPS, engine="auto", lanes=0,
+                 swarm_id=0, trace_cap=0):
+        from paper_2110_01470_amd.binding import Swarm
+
+        self.kind, self.n, self.d = kind, n, d
+        self.s, self.w, self.a = make_objective(kind, d, seed, *s_range)
+        self.orc = oracle.Swarm(n, d, KIND[kind], lo, hi, cg, cp, cw, seed, self.s, self.w,
+                                self.a, swarm=swarm_id, order=order)
+        self.gpu = Swarm(n, d, kind, lo, hi, cg, cp, cw, seed, self.s, self.w, self.a,
+                         swarm_id=swarm_id, order=order, engine=engine, lanes=lanes,
+                         trace_cap=trace_cap)
+        self.orc.init()
+        self.band_events = 0
+        self.prev_fp64 = self.orc.fp64.copy()
+
+    def step(self, k=1):
+        """k generations on both sides, comparing after each."""
+        for _ in range(k):
+            self.prev_fp64 = self.orc.fp64.copy()
+            self.orc.step()
+            self.gpu.step()
+            self.compare()
+
+    def compare(self, check_fitness=True):
+        orc, gpu = self.orc, self.gpu
+        x, p, fp, t = gpu.state()
+        assert t == orc.t
+        assert np.array_equal(x, orc.x), _first_diff(x, orc.x, "x")
+        resync = False
+        rows = np.where(~np.all(p == orc.p, axis=1))[0]
+        for i in rows:
+            # The GPU and the oracle took different pBest decisions for i.
+            assert near(orc.fx64[i], self.prev_fp64[i]), (
+                f"pBest decision of particle {i} differs outside the band: "
+                f"f(x')={orc.fx64[i]!r} fP={self.prev_fp64[i]!r}")
+            resync = True
+        same = np.ones(self.n, bool)
+        same[rows] = False
+        if check_fitness:
+            ref = orc.fp64[same]
+            got = fp[same].astype(np.float64)
+            err = np.abs(got - ref)
+            lim = REL_TOL * np.abs(ref)
+            bad = np.where(err > lim)[0]
+            assert bad.size == 0, (
+                f"fitness off by more than {REL_TOL} relative at {bad[:5]}: "
+                f"{got[bad[:5]]} vs {ref[bad[:5]]}")
+        g, fg, gidx, gen = gpu.best()
+        assert gen == orc.t
+        assert np.array_equal(g, p[gidx])
+        if gidx != orc.gidx:
+            assert near(orc.fp64[gidx], orc.fp64[orc.gidx]) or resync, (
+                f"gBest index {gidx} vs oracle {orc.gidx} outside the band")
+            resync = True
+        else:
+            assert np.array_equal(g, orc.g)
+            if check_fitness:
+                assert near(fg, orc.fp64[orc.gidx], REL_TOL)
+        if resync:
+            self.band_events += 1
+            gpu.set_state(orc.x, orc.p, orc.fp, orc.t)
+
+
+def _first_diff(a, b, name):
+    idx = np.argwhere(a != b)
+    if idx.size == 0:
+        return f"{name} equal"
+    i = tuple(idx[0])
+    return f"{name} differs at {i}: {a[i]!r} vs {b[i]!r} ({len(idx)} elements differ)"

