@@ -24,7 +24,7 @@
 
 namespace sso {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef f4 floatx4;
 
 constexpr int kDenseWaves = 4;
 constexpr int kDenseBlock = 64 * kDenseWaves;
@@ -69,13 +69,6 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     // A is handled as native 4-vectors: arrays of them stay in registers.
     const floatx4 *a_pack = reinterpret_cast<const floatx4 *>(S.a);
 
-    const float *grow_ptr = S.rows;
-    if constexpr (!INIT) {
-        const unsigned long long gk = S.keys[(t - 1u) % S.trace_cap];
-        const uint32_t glow = (uint32_t)gk;
-        const uint32_t gidx = min(glow >> 1, S.n - 1u);
-        grow_ptr = S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.dp;
-    }
     uint32_t prow = 0;
     bool alias = true;
     float fpi = 0.0f;
@@ -85,13 +78,19 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
         prow = st & ST_ROW;
         alias = (st & ST_ALIAS) != 0u;
     }
+    const float *grow_ptr = S.rows;
+    if constexpr (!INIT) {
+        const uint32_t glow = (uint32_t)generation_begin(S, t);
+        const uint32_t gidx = min(glow >> 1, S.n - 1u);
+        grow_ptr = S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.dp;
+    }
     const size_t ioff = (size_t)(valid ? i : 0u) * S.dp;
-    const float4 *p4 = reinterpret_cast<const float4 *>(S.rows + prow * S.buf + ioff);
-    float4 *x4 = reinterpret_cast<float4 *>(S.rows + (INIT ? 0u : (1u - prow)) * S.buf + ioff);
+    const f4 *p4 = reinterpret_cast<const f4 *>(S.rows + prow * S.buf + ioff);
+    f4 *x4 = reinterpret_cast<f4 *>(S.rows + (INIT ? 0u : (1u - prow)) * S.buf + ioff);
     // Where the position is read from: the pBest row itself when aliased.
-    const float4 *xsrc = alias ? p4 : x4;
-    const float4 *g4 = reinterpret_cast<const float4 *>(grow_ptr);
-    const float4 *s4 = reinterpret_cast<const float4 *>(S.s);
+    const f4 *xsrc = alias ? p4 : x4;
+    const f4 *g4 = reinterpret_cast<const f4 *>(grow_ptr);
+    const f4 *s4 = reinterpret_cast<const f4 *>(S.s);
 
     // Stage K-chunk 0.
     floatx4 stage[PER];
@@ -102,8 +101,8 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     }
 
     // Row operands of the first chunk this lane selects.
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 pv = zero4, xv = zero4, gv = zero4;
+    const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
+    f4 pv = zero4, xv = zero4, gv = zero4;
     if (!INIT && valid && grp < S.chunks) {
         pv = p4[grp];
         xv = xsrc[grp];
@@ -132,18 +131,16 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
         }
         // Select this lane's chunk c = 4M + grp by Eq. (2.1) and form d = x' - s.
         const uint32_t c = 4u * M + grp;
-        float4 dv = zero4;
+        f4 dv = zero4;
         if (valid && c < S.chunks) {
             const uint4 k = words4(S, c, i, t);
-            float4 xn;
-            if constexpr (INIT) {
-                xn = make_float4(init_value(S, k.x), init_value(S, k.y), init_value(S, k.z),
-                                 init_value(S, k.w));
-            } else {
+            f4 xn;
+            if constexpr (INIT)
+                xn = init4(S, k);
+            else
                 xn = select4<EQ21>(S, k, gv, pv, xv);
-            }
             x4[c] = xn;
-            const float4 sv = s4[c];
+            const f4 sv = s4[c];
             const uint32_t j0 = 4u * c;
             dv.x = (j0 + 0 < S.d) ? xn.x - sv.x : 0.f;
             dv.y = (j0 + 1 < S.d) ? xn.y - sv.y : 0.f;
@@ -209,14 +206,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
         if (improved) S.fp[i] = fnew;
     }
     const unsigned long long key = valid ? gbest_key(fnew, i, row) : ~0ull;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const uint32_t nx = (t + 1u) % S.trace_cap;
-        S.keys[nx] = ~0ull;
-        S.cnt[nx] = 0u;
-    }
-    const uint32_t slot = t % S.trace_cap;
-    workgroup_commit<kDenseWaves>(key, (improved && grp == 0) ? 1u : 0u, S.keys + slot,
-                                  S.cnt + slot);
+    generation_commit<kDenseWaves>(S, t, key, (improved && grp == 0) ? 1u : 0u);
 }
 
 template <int NB>

@@ -21,6 +21,7 @@
 namespace sso {
 
 constexpr int kWaves = 4;
+constexpr int kInFlight = 4;  // chunks whose loads a lane issues before computing
 
 template <int KIND, int L, bool EQ21, bool INIT>
 __global__ __launch_bounds__(64 * kWaves) void k_stream(SwarmDev S, uint32_t t)
@@ -31,50 +32,62 @@ __global__ __launch_bounds__(64 * kWaves) void k_stream(SwarmDev S, uint32_t t)
     const uint32_t i = (blockIdx.x * kWaves + wave) * G + lane / L;
     const bool valid = i < S.n;
 
-    // gBest of the previous generation (unused at t == 0).
-    const float *grow_ptr = nullptr;
-    if constexpr (!INIT) {
-        const unsigned long long gk = S.keys[(t - 1u) % S.trace_cap];
-        const uint32_t glow = (uint32_t)gk;
-        const uint32_t gidx = min(glow >> 1, S.n - 1u);
-        grow_ptr = S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.dp;
-    }
-
-    uint32_t st = 0, prow = 0;
+    uint32_t prow = 0;
     bool alias = true;
     float fpi = 0.0f;
     if (!INIT && valid) {
-        st = S.st[i];
+        const uint32_t st = S.st[i];
         fpi = S.fp[i];
         prow = st & ST_ROW;
         alias = (st & ST_ALIAS) != 0u;
     }
-    const size_t ioff = (size_t)i * S.dp;
-    const float4 *prow_ptr = reinterpret_cast<const float4 *>(S.rows + prow * S.buf + ioff);
+    // gBest of the previous generation (unused at t == 0).
+    const f4 *g4 = nullptr;
+    if constexpr (!INIT) {
+        const uint32_t glow = (uint32_t)generation_begin(S, t);
+        const uint32_t gidx = min(glow >> 1, S.n - 1u);
+        g4 = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.dp);
+    }
+    const size_t ioff = (size_t)(valid ? i : 0u) * S.dp;
+    const f4 *p4 = reinterpret_cast<const f4 *>(S.rows + prow * S.buf + ioff);
     // INIT writes the pBest row (row 0); a generation writes the other row.
-    float4 *xrow_ptr = reinterpret_cast<float4 *>(S.rows + (INIT ? 0u : (1u - prow)) * S.buf + ioff);
-    const float4 *g4 = reinterpret_cast<const float4 *>(grow_ptr);
-    const float4 *s4 = reinterpret_cast<const float4 *>(S.s);
-    const float4 *w4 = reinterpret_cast<const float4 *>(S.w);
+    f4 *x4 = reinterpret_cast<f4 *>(S.rows + (INIT ? 0u : (1u - prow)) * S.buf + ioff);
+    // The position is read from the pBest row itself when aliased.
+    const f4 *xsrc = alias ? p4 : x4;
+    const f4 *s4 = reinterpret_cast<const f4 *>(S.s);
+    const f4 *w4 = reinterpret_cast<const f4 *>(S.w);
+    const f4 zero = f4{0.f, 0.f, 0.f, 0.f};
 
     float acc = 0.0f;
     if (valid) {
-        for (uint32_t c = ln; c < S.chunks; c += L) {
-            const uint4 k = words4(S, c, i, t);
-            float4 xn;
-            if constexpr (INIT) {
-                xn = make_float4(init_value(S, k.x), init_value(S, k.y), init_value(S, k.z),
-                                 init_value(S, k.w));
-            } else {
-                const float4 p = prow_ptr[c];
-                const float4 x = alias ? p : xrow_ptr[c];
-                const float4 g = g4[c];
-                xn = select4<EQ21>(S, k, g, p, x);
+        for (uint32_t c0 = ln; c0 < S.chunks; c0 += kInFlight * L) {
+            f4 pv[kInFlight], xv[kInFlight], gv[kInFlight];
+            if constexpr (!INIT) {
+#pragma unroll
+                for (int u = 0; u < kInFlight; ++u) {
+                    const uint32_t c = c0 + u * L;
+                    if (c < S.chunks) {
+                        pv[u] = p4[c];
+                        xv[u] = xsrc[c];
+                        gv[u] = g4[c];
+                    }
+                }
             }
-            xrow_ptr[c] = xn;
-            const float4 sv = s4[c];
-            const float4 wv = (KIND == OBJ_RIPPLE) ? w4[c] : make_float4(0.f, 0.f, 0.f, 0.f);
-            acc += terms4<KIND>(xn, sv, wv, 4u * c, S.d);
+#pragma unroll
+            for (int u = 0; u < kInFlight; ++u) {
+                const uint32_t c = c0 + u * L;
+                if (c < S.chunks) {
+                    const uint4 k = words4(S, c, i, t);
+                    f4 xn;
+                    if constexpr (INIT)
+                        xn = init4(S, k);
+                    else
+                        xn = select4<EQ21>(S, k, gv[u], pv[u], xv[u]);
+                    x4[c] = xn;
+                    const f4 wv = (KIND == OBJ_RIPPLE) ? w4[c] : zero;
+                    acc += terms4<KIND>(xn, s4[c], wv, 4u * c, S.d);
+                }
+            }
         }
     }
 #pragma unroll
@@ -94,13 +107,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_stream(SwarmDev S, uint32_t t)
     }
     const unsigned long long key = valid ? gbest_key(fnew, i, row) : ~0ull;
 
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const uint32_t nx = (t + 1u) % S.trace_cap;
-        S.keys[nx] = ~0ull;
-        S.cnt[nx] = 0u;
-    }
-    const uint32_t slot = t % S.trace_cap;
-    workgroup_commit<kWaves>(key, (improved && ln == 0) ? 1u : 0u, S.keys + slot, S.cnt + slot);
+    generation_commit<kWaves>(S, t, key, (improved && ln == 0) ? 1u : 0u);
 }
 
 template <int KIND, int L, bool EQ21>
@@ -142,22 +149,27 @@ int launch_stream_generation(const SwarmDev &S, uint32_t t, uint32_t lanes, void
     return (int)hipErrorInvalidValue;
 }
 
-// Clears the whole trace ring: keys to "no gBest yet", counts to zero.  A
-// kernel rather than a memset so the clear can sit inside a captured graph.
-__global__ void k_fill_trace(unsigned long long *keys, uint32_t *cnt, uint32_t cap)
+// Clears the trace ring (keys to "no gBest yet", counts to zero) and every
+// sub-slot group.  A kernel rather than a memset so the clear can sit inside
+// a captured graph.
+__global__ void k_fill_trace(SwarmDev S)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < cap) {
-        keys[j] = ~0ull;
-        cnt[j] = 0u;
+    if (j < S.trace_cap) {
+        S.keys[j] = ~0ull;
+        S.cnt[j] = 0u;
+    }
+    if (j < kGroups * kSubSlots) {
+        *sub_key(S, j / kSubSlots, j % kSubSlots) = ~0ull;
+        *sub_cnt(S, j / kSubSlots, j % kSubSlots) = 0u;
     }
 }
 
 int launch_fill_trace(const SwarmDev &S, void *stream)
 {
-    const uint32_t blocks = (S.trace_cap + 255u) / 256u;
-    hipLaunchKernelGGL(k_fill_trace, dim3(blocks), dim3(256), 0, (hipStream_t)stream, S.keys,
-                       S.cnt, S.trace_cap);
+    const uint32_t items = S.trace_cap > kGroups * kSubSlots ? S.trace_cap : kGroups * kSubSlots;
+    const uint32_t blocks = (items + 255u) / 256u;
+    hipLaunchKernelGGL(k_fill_trace, dim3(blocks), dim3(256), 0, (hipStream_t)stream, S);
     return (int)hipGetLastError();
 }
 

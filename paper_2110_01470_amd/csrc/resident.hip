@@ -3,7 +3,7 @@
 //
 // A generation of Algorithm 2 on a swarm like N=100, D=30 is 3,000 variable
 // updates -- far too little to hide a kernel launch.  Here every lane owns
-// one float4 chunk of one particle (L lanes per particle, L = chunks rounded
+// one 4-float chunk of one particle (L lanes per particle, L = chunks rounded
 // up to a power of two), keeps X and P of that chunk in registers, and only
 // gBest and the argmin travel through LDS.  Per generation: Eq. (2.1) select
 // and objective terms in registers, an L-lane butterfly for the fitness, the
@@ -41,7 +41,7 @@ template <int KIND, int L, bool EQ21>
 __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, uint32_t t_first,
                                                                  uint32_t generations)
 {
-    __shared__ float4 s_g[kDenseMaxD / 4];
+    __shared__ f4 s_g[kDenseMaxD / 4];
     __shared__ unsigned long long s_key[kResidentMaxWaves];
     __shared__ uint32_t s_cnt[kResidentMaxWaves];
 
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, ui
     const bool owns = valid && c < S.chunks;     // lane holds real variables
 
     // Load the state of generation t_first - 1.
-    float4 xv = make_float4(0.f, 0.f, 0.f, 0.f), pv = xv, sv = xv, wv = xv;
+    f4 xv = f4{0.f, 0.f, 0.f, 0.f}, pv = xv, sv = xv, wv = xv;
     float fp = 0.0f;
     if (valid) {
         const uint32_t st = S.st[i];
@@ -65,20 +65,39 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, ui
             const size_t off = (size_t)i * S.dp;
             const float *prow_ptr = S.rows + prow * S.buf + off;
             const float *xrow_ptr = (st & ST_ALIAS) ? prow_ptr : S.rows + (1u - prow) * S.buf + off;
-            pv = reinterpret_cast<const float4 *>(prow_ptr)[c];
-            xv = reinterpret_cast<const float4 *>(xrow_ptr)[c];
+            pv = reinterpret_cast<const f4 *>(prow_ptr)[c];
+            xv = reinterpret_cast<const f4 *>(xrow_ptr)[c];
         }
     }
     if (c < S.chunks) {
-        sv = reinterpret_cast<const float4 *>(S.s)[c];
-        if (KIND == OBJ_RIPPLE) wv = reinterpret_cast<const float4 *>(S.w)[c];
+        sv = reinterpret_cast<const f4 *>(S.s)[c];
+        if (KIND == OBJ_RIPPLE) wv = reinterpret_cast<const f4 *>(S.w)[c];
     }
     {
-        const unsigned long long gk = S.keys[(t_first - 1u) % S.trace_cap];
+        // gBest of generation t_first - 1 from its sub-slot group; also
+        // records that generation in the trace ring.
+        __shared__ unsigned long long s_first;
+        if (threadIdx.x < 64u) {
+            const uint32_t g = (t_first - 1u) % kGroups;
+            unsigned long long k = *sub_key(S, g, lane);
+            uint32_t cc = *sub_cnt(S, g, lane);
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) {
+                k = min_u64(k, shfl_xor_u64(k, m));
+                cc += __shfl_xor(cc, m, 64);
+            }
+            if (lane == 0) {
+                s_first = k;
+                S.keys[(t_first - 1u) % S.trace_cap] = k;
+                S.cnt[(t_first - 1u) % S.trace_cap] = cc;
+            }
+        }
+        __syncthreads();
+        const unsigned long long gk = s_first;
         const uint32_t glow = (uint32_t)gk;
         const uint32_t gidx = min(glow >> 1, S.n - 1u);
-        const float4 *grow = reinterpret_cast<const float4 *>(S.rows + (size_t)(glow & 1u) * S.buf +
-                                                              (size_t)gidx * S.dp);
+        const f4 *grow = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf +
+                                                      (size_t)gidx * S.dp);
         for (uint32_t q = threadIdx.x; q < S.chunks; q += blockDim.x) s_g[q] = grow[q];
     }
     __syncthreads();
@@ -125,18 +144,25 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, ui
     if (valid) {
         const size_t off = (size_t)i * S.dp;
         if (owns) {
-            reinterpret_cast<float4 *>(S.rows + off)[c] = pv;
-            reinterpret_cast<float4 *>(S.rows + S.buf + off)[c] = xv;
+            reinterpret_cast<f4 *>(S.rows + off)[c] = pv;
+            reinterpret_cast<f4 *>(S.rows + S.buf + off)[c] = xv;
         }
         if (c == 0) {
             S.st[i] = 0u;
             S.fp[i] = fp;
         }
     }
-    if (threadIdx.x == 0) {
-        const uint32_t nx = (t_first + generations) % S.trace_cap;
-        S.keys[nx] = ~0ull;
-        S.cnt[nx] = 0u;
+    // Leave the last generation's result where a following generation (and
+    // the host) looks for it: sub-slot 0 of its group; clear the other groups.
+    if (threadIdx.x < 64u) {
+        const uint32_t tl = t_first + generations - 1u;
+        const unsigned long long best = S.keys[tl % S.trace_cap];
+        const uint32_t total = S.cnt[tl % S.trace_cap];
+        for (uint32_t g = 0; g < kGroups; ++g) {
+            const bool mine = g == tl % kGroups && lane == 0;
+            *sub_key(S, g, lane) = mine ? best : ~0ull;
+            *sub_cnt(S, g, lane) = mine ? total : 0u;
+        }
     }
 }
 

@@ -39,7 +39,7 @@ size_t align256(size_t x) { return (x + 255u) & ~(size_t)255u; }
 uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 
 struct Layout {
-    size_t rows, fp, st, s, w, a, keys, cnt, total;
+    size_t rows, fp, st, s, w, a, keys, cnt, sub, total;
     uint32_t dp, trace_cap;
 };
 
@@ -57,6 +57,7 @@ Layout make_layout(const sso_config &c)
     L.a = off;    off += c.kind == SSO_OBJ_DENSE ? align256(dense_matrix_floats(c.d) * sizeof(float)) : 0;
     L.keys = off; off += align256((size_t)L.trace_cap * sizeof(unsigned long long));
     L.cnt = off;  off += align256((size_t)L.trace_cap * sizeof(uint32_t));
+    L.sub = off;  off += align256((size_t)kSubWords * sizeof(unsigned long long));
     L.total = off;
     return L;
 }
@@ -138,6 +139,28 @@ float from_orderable(uint32_t o)
     float f;
     std::memcpy(&f, &b, 4);
     return f;
+}
+
+// gBest key and improvement count of generation t, from its sub-slot group
+// (the trace ring holds a generation only once the next one has run).
+int current_result(sso_ctx *ctx, unsigned long long *key, uint32_t *count)
+{
+    const SwarmDev &S = ctx->S;
+    std::vector<unsigned long long> grp((size_t)kSubSlots * kSubStride);
+    const unsigned long long *src = S.sub + (size_t)(ctx->t % kGroups) * kSubSlots * kSubStride;
+    HIP_TRY(&ctx->err, hipMemcpy(grp.data(), src, sizeof(unsigned long long) * grp.size(), hipMemcpyDeviceToHost));
+    unsigned long long k = ~0ull;
+    uint32_t c = 0;
+    for (uint32_t j = 0; j < kSubSlots; ++j) {
+        const unsigned long long kj = grp[(size_t)j * kSubStride];
+        uint32_t cj;
+        std::memcpy(&cj, &grp[(size_t)j * kSubStride + 1], sizeof cj);
+        if (kj < k) k = kj;
+        c += cj;
+    }
+    *key = k;
+    *count = c;
+    return SSO_OK;
 }
 
 int launch_generations(sso_ctx *ctx, uint64_t t_first, uint32_t count)
@@ -236,6 +259,7 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
     S.a = cfg->kind == SSO_OBJ_DENSE ? (const float *)(base + L.a) : nullptr;
     S.keys = (unsigned long long *)(base + L.keys);
     S.cnt = (uint32_t *)(base + L.cnt);
+    S.sub = (unsigned long long *)(base + L.sub);
     S.buf = (uint64_t)cfg->n * L.dp;
     S.n = cfg->n;
     S.d = cfg->d;
@@ -252,6 +276,7 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
     S.r = (uint32_t)((1ull << 56) / ((1ull << 32) - th2));
     S.lo = cfg->lo;
     S.span = cfg->hi - cfg->lo;
+    S.span24 = std::ldexp(S.span, -24);
     S.key0 = (uint32_t)cfg->seed;
     S.key1 = (uint32_t)(cfg->seed >> 32);
     S.swarm = cfg->swarm_id;
@@ -312,7 +337,9 @@ int sso_get_best(sso_ctx *ctx, float *g_out, float *f_out, uint32_t *idx_out, ui
     const SwarmDev &S = ctx->S;
     HIP_TRY(&ctx->err, hipStreamSynchronize(ctx->stream));
     unsigned long long key = 0;
-    HIP_TRY(&ctx->err, hipMemcpy(&key, S.keys + ctx->t % S.trace_cap, sizeof key, hipMemcpyDeviceToHost));
+    uint32_t count = 0;
+    const int rc = current_result(ctx, &key, &count);
+    if (rc != SSO_OK) return rc;
     const uint32_t low = (uint32_t)key;
     const uint32_t gidx = low >> 1, row = low & 1u;
     if (gidx >= S.n) {
@@ -386,6 +413,9 @@ int sso_set_state(sso_ctx *ctx, const float *x, const float *p, const float *fp,
     HIP_TRY(&ctx->err, hipStreamSynchronize(ctx->stream));
     HIP_TRY(&ctx->err, hipMemcpy(S.keys + t % S.trace_cap, &best, sizeof best, hipMemcpyHostToDevice));
     HIP_TRY(&ctx->err, hipMemcpy(S.cnt + t % S.trace_cap, &zero, sizeof zero, hipMemcpyHostToDevice));
+    // The next generation finds gBest in sub-slot 0 of generation t's group.
+    unsigned long long *slot0 = S.sub + (size_t)(t % kGroups) * kSubSlots * kSubStride;
+    HIP_TRY(&ctx->err, hipMemcpy(slot0, &best, sizeof best, hipMemcpyHostToDevice));
     ctx->t = t;
     ctx->trace_base = t;
     return SSO_OK;
@@ -407,6 +437,14 @@ int sso_get_trace(sso_ctx *ctx, uint64_t first, uint32_t count, float *fg, uint3
     std::vector<uint32_t> cnt(S.trace_cap);
     HIP_TRY(&ctx->err, hipMemcpy(keys.data(), S.keys, sizeof(unsigned long long) * S.trace_cap, hipMemcpyDeviceToHost));
     HIP_TRY(&ctx->err, hipMemcpy(cnt.data(), S.cnt, sizeof(uint32_t) * S.trace_cap, hipMemcpyDeviceToHost));
+    if (last == ctx->t) {
+        unsigned long long key = 0;
+        uint32_t c = 0;
+        const int rc = current_result(ctx, &key, &c);
+        if (rc != SSO_OK) return rc;
+        keys[ctx->t % S.trace_cap] = key;
+        cnt[ctx->t % S.trace_cap] = c;
+    }
     for (uint32_t k = 0; k < count; ++k) {
         const uint32_t slot = (uint32_t)((first + k) % S.trace_cap);
         if (fg) fg[k] = from_orderable((uint32_t)(keys[slot] >> 32));

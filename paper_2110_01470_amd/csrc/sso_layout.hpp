@@ -25,6 +25,18 @@ enum : uint32_t { ST_ROW = 1u, ST_ALIAS = 2u };
 constexpr uint32_t kRowAlign = 32;      // floats per row alignment unit (128 B)
 constexpr uint32_t kDenseMaxD = 256;    // dense kernel limit on d
 
+// gBest hand-off between generations.  Every workgroup folds its (fitness,
+// index) key and improvement count into one of kSubSlots sub-slots of the
+// generation's group with device-scope atomics; sub-slots sit kSubStride
+// 64-bit words (256 B) apart so the atomics of different workgroups do not
+// serialise on one line.  Groups rotate over kGroups generations: generation
+// t commits into group t % 3, reduces group (t - 1) % 3 to find gBest of the
+// previous generation, and its workgroup 0 clears group (t + 1) % 3.
+constexpr uint32_t kSubSlots = 64;
+constexpr uint32_t kSubStride = 32;
+constexpr uint32_t kGroups = 3;
+constexpr uint32_t kSubWords = kGroups * kSubSlots * kSubStride;  // 64-bit words
+
 struct SwarmDev {
     float *rows;                 // [2][n][dp]
     float *fp;                   // [n] pBest fitness (FP32)
@@ -32,13 +44,14 @@ struct SwarmDev {
     const float *s;              // [dp] shift, zero padded
     const float *w;              // [dp] ripple weights, zero padded (or null)
     const float *a;              // dense matrix, layout of the dense kernel (or null)
-    unsigned long long *keys;    // [trace_cap] gBest key per generation (ring)
-    uint32_t *cnt;               // [trace_cap] improved pBests per generation (ring)
+    unsigned long long *keys;    // [trace_cap] gBest key per finished generation (ring)
+    uint32_t *cnt;               // [trace_cap] improved pBests per finished generation (ring)
+    unsigned long long *sub;     // [kGroups][kSubSlots][kSubStride]: key, then count
     uint64_t buf;                // floats from row buffer 0 to row buffer 1 (n * dp)
     uint32_t n, d, dp, chunks;   // chunks = ceil(d / 4)
     uint32_t trace_cap;
     uint32_t th0, th1, th2, r;   // integer thresholds and fresh-draw rescale
-    float lo, span;
+    float lo, span, span24;      // span24 = span * 2^-24 (exact)
     uint32_t key0, key1, swarm;  // Philox key and fourth counter word
     int32_t kind, order;
 };
@@ -46,7 +59,7 @@ struct SwarmDev {
 // Launchers (each returns hipSuccess or the launch error).
 int launch_stream_generation(const SwarmDev &S, uint32_t t, uint32_t lanes, void *stream);
 int launch_dense_generation(const SwarmDev &S, uint32_t t, void *stream);
-int launch_fill_trace(const SwarmDev &S, void *stream);
+int launch_fill_trace(const SwarmDev &S, void *stream);  // clears trace ring and sub-slot groups
 int launch_debug_rng(const SwarmDev &S, uint32_t t, uint32_t *out, void *stream);
 int launch_resident(const SwarmDev &S, uint32_t t_first, uint32_t generations, void *stream);
 bool resident_fits(uint32_t n, uint32_t d, int kind);
