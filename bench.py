@@ -104,6 +104,22 @@ def time_oracle(wl, gens):
     return time.perf_counter() - t0
 
 
+def copy_calibration(nbytes, reps=5):
+    """A plain device-to-device copy of known size, for scaling HBM counters."""
+    import torch
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps, "seconds_per_copy": sec,
+                      "GBps_read_plus_write": 2 * nbytes / sec / 1e9}), flush=True)
+
+
 def main():
     from paper_2110_01470_amd.inputs import WORKLOADS
 
@@ -115,7 +131,13 @@ def main():
     ap.add_argument("--engine", default="auto", choices=["auto", "stream", "resident"])
     ap.add_argument("--cpu-gens", type=int, default=None,
                     help="oracle generations for cpu_baseline (0 = skip)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_bytes:
+        copy_calibration(args.copy_bytes)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "

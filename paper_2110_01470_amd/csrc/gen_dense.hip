@@ -1,11 +1,16 @@
 // Dense objective f(x) = ||A (x - s)||^2: one fused kernel per generation
 // with the contraction on FP32 matrix cores (v_mfma_f32_16x16x4_f32).
 //
-// Work split: a workgroup of four waves owns 64 particles, a wave owns 16.
-// Per wave the kernel forms Y^T = A * D^T (rows: output index k of A,
-// columns: the wave's 16 particles, inner index: variable j), where
-// D = X' - s is produced on the fly by the Eq. (2.1) select of the same
-// generation, and the fitness of particle p is the sum over k of Y^T[k][p]^2.
+// Work split: a workgroup of eight waves owns 64 particles in four groups
+// of 16.  The two waves of a group split the inner index: wave half h
+// selects (Eq. 2.1) and contracts the variables of K-chunks
+// [h NB/2, (h+1) NB/2), each K-chunk being 16 variables.  Per wave the kernel
+// forms a partial Y^T = A[:, its chunks] * D^T[its chunks, :] (rows: output
+// index k of A, columns: the group's 16 particles), where D = X' - s comes
+// straight out of the select of the same generation.  At the end the upper
+// half adds its partial Y^T into the lower half's through LDS, and the
+// fitness of particle p is the sum over k of Y^T[k][p]^2.  Two waves per
+// SIMD let one wave's select (VALU, memory) run under the other's MFMAs.
 //
 // MFMA operand layout (16x16x4, one block): lane l supplies A-operand
 // element (row l%16, inner l/16) and B-operand element (inner l/16,
@@ -18,15 +23,16 @@
 //   * the A operands are one float4 per lane and row block; the host packs A
 //     as [M][row block][lane][4] so that K-chunk M is one contiguous block
 //     that the workgroup copies into LDS and each wave reads conflict-free.
-// K-chunks are double-buffered in LDS; the next chunk's global loads and the
-// next select's row loads are issued before the current chunk's MFMAs.
+// The two K-chunks of a step (one per half) are double-buffered in LDS; the
+// next step's global loads and the next select's row loads are issued
+// before the current step's MFMAs.
 #include "sso_device.hpp"
 
 namespace sso {
 
 typedef f4 floatx4;
 
-constexpr int kDenseWaves = 4;
+constexpr int kDenseWaves = 8;
 constexpr int kDenseBlock = 64 * kDenseWaves;
 
 uint64_t dense_matrix_floats(uint32_t d)
@@ -52,22 +58,27 @@ void dense_pack_matrix(const float *a, uint32_t d, float *out)
                 }
 }
 
-// NB = dp / 16: row blocks of A, and K-chunks of 16 variables.
+// NB = dp / 16: row blocks of A, and K-chunks of 16 variables (NB is even).
 template <int NB, bool EQ21, bool INIT>
 __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
 {
-    constexpr uint32_t CF4 = NB * 64u;                          // float4 per K-chunk
-    constexpr uint32_t PER = (CF4 + kDenseBlock - 1) / kDenseBlock;  // per thread
-    constexpr bool FULL = CF4 % kDenseBlock == 0;
-    __shared__ floatx4 lds_a[2][CF4];
+    constexpr uint32_t HALF = NB / 2;                               // K-chunks per wave
+    constexpr uint32_t CF4 = NB * 64u;                              // float4 per K-chunk
+    constexpr uint32_t STEP_F4 = 2 * CF4;                           // both halves' chunks
+    constexpr uint32_t PER = (STEP_F4 + kDenseBlock - 1) / kDenseBlock;
+    constexpr bool FULL = STEP_F4 % kDenseBlock == 0;
+    // Two step buffers; after the loop the same memory carries the upper
+    // halves' partial accumulators (4 groups x NB x 64 lanes x 4 floats).
+    static_assert(2 * STEP_F4 >= 4 * NB * 64, "reduction buffer fits the staging buffers");
+    __shared__ f4 lds[2][STEP_F4];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u, wave = tid >> 6;
-    const uint32_t pcol = lane & 15u, grp = lane >> 4;
-    const uint32_t i = blockIdx.x * 64u + wave * 16u + pcol;
+    const uint32_t grp4 = wave & 3u, half = wave >> 2;   // particle group, K half
+    const uint32_t pcol = lane & 15u, lg = lane >> 4;
+    const uint32_t i = blockIdx.x * 64u + grp4 * 16u + pcol;
     const bool valid = i < S.n;
-    // A is handled as native 4-vectors: arrays of them stay in registers.
-    const floatx4 *a_pack = reinterpret_cast<const floatx4 *>(S.a);
+    const f4 *a_pack = reinterpret_cast<const f4 *>(S.a);
 
     uint32_t prow = 0;
     bool alias = true;
@@ -92,45 +103,47 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     const f4 *g4 = reinterpret_cast<const f4 *>(grow_ptr);
     const f4 *s4 = reinterpret_cast<const f4 *>(S.s);
 
-    // Stage K-chunk 0.
-    floatx4 stage[PER];
+    // Step m stages K-chunk m (lower half) and K-chunk HALF + m (upper half).
+    auto stage_addr = [&](uint32_t m, uint32_t q) -> size_t {
+        return (size_t)(q < CF4 ? m : HALF + m) * CF4 + (q % CF4);
+    };
 #pragma unroll
     for (uint32_t r = 0; r < PER; ++r) {
         const uint32_t q = tid + r * kDenseBlock;
-        if (FULL || q < CF4) lds_a[0][q] = a_pack[q];
+        if (FULL || q < STEP_F4) lds[0][q] = a_pack[stage_addr(0, q)];
     }
 
-    // Row operands of the first chunk this lane selects.
+    // Row operands (and shift) of the first chunk this lane selects.
+    const uint32_t cbase = 4u * HALF * half;  // first chunk of this wave's half
     const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
-    f4 pv = zero4, xv = zero4, gv = zero4;
-    if (!INIT && valid && grp < S.chunks) {
-        pv = p4[grp];
-        xv = xsrc[grp];
-        gv = g4[grp];
-    }
+    f4 pv = zero4, xv = zero4, gv = zero4, sv = zero4;
+    auto prefetch = [&](uint32_t c) {
+        if (valid && c < S.chunks) {
+            sv = s4[c];
+            if constexpr (!INIT) {
+                pv = p4[c];
+                xv = xsrc[c];
+                gv = g4[c];
+            }
+        }
+    };
+    prefetch(cbase + lg);
 
-    floatx4 acc[NB];
+    f4 acc[NB];
 #pragma unroll
-    for (uint32_t rb = 0; rb < NB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (uint32_t rb = 0; rb < NB; ++rb) acc[rb] = zero4;
 
     __syncthreads();
 
-    // Fully unrolled over the K-chunks, so the staging registers and the
-    // double-buffer index are compile-time.
+    // Per step: select from operands fetched one step earlier, then issue the
+    // next step's row and A loads, then the MFMAs; the only wait on global
+    // memory is before the staging write at the end of the step.
 #pragma unroll
-    for (uint32_t M = 0; M < NB; ++M) {
-        const uint32_t cur = M & 1u;
-        const bool more = M + 1 < NB;
-        // Issue the next K-chunk's global loads; they land in LDS after the MFMAs.
-        if (more) {
-#pragma unroll
-            for (uint32_t r = 0; r < PER; ++r) {
-                const uint32_t q = tid + r * kDenseBlock;
-                if (FULL || q < CF4) stage[r] = a_pack[(size_t)(M + 1) * CF4 + q];
-            }
-        }
-        // Select this lane's chunk c = 4M + grp by Eq. (2.1) and form d = x' - s.
-        const uint32_t c = 4u * M + grp;
+    for (uint32_t m = 0; m < HALF; ++m) {
+        const uint32_t cur = m & 1u;
+        const bool more = m + 1 < HALF;
+        // Select this lane's chunk c of Eq. (2.1) and form d = x' - s.
+        const uint32_t c = cbase + 4u * m + lg;
         f4 dv = zero4;
         if (valid && c < S.chunks) {
             const uint4 k = words4(S, c, i, t);
@@ -140,24 +153,26 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
             else
                 xn = select4<EQ21>(S, k, gv, pv, xv);
             x4[c] = xn;
-            const f4 sv = s4[c];
             const uint32_t j0 = 4u * c;
             dv.x = (j0 + 0 < S.d) ? xn.x - sv.x : 0.f;
             dv.y = (j0 + 1 < S.d) ? xn.y - sv.y : 0.f;
             dv.z = (j0 + 2 < S.d) ? xn.z - sv.z : 0.f;
             dv.w = (j0 + 3 < S.d) ? xn.w - sv.w : 0.f;
         }
-        // Prefetch the row operands of the next chunk.
-        if (!INIT && more && valid && c + 4u < S.chunks) {
-            pv = p4[c + 4u];
-            xv = xsrc[c + 4u];
-            gv = g4[c + 4u];
+        f4 stage[PER];
+        if (more) {
+            prefetch(c + 4u);
+#pragma unroll
+            for (uint32_t r = 0; r < PER; ++r) {
+                const uint32_t q = tid + r * kDenseBlock;
+                if (FULL || q < STEP_F4) stage[r] = a_pack[stage_addr(m + 1, q)];
+            }
         }
 
-        // Y^T += A[:, chunk M] * D^T[chunk M, :] for every row block; the
+        // Y^T += A[:, chunk] * D^T[chunk, :] for every row block; the
         // e-outer order keeps consecutive MFMAs on different accumulators.
-        const floatx4 *la = lds_a[cur];
-        floatx4 av[NB];
+        const f4 *la = lds[cur] + half * CF4;
+        f4 av[NB];
 #pragma unroll
         for (uint32_t rb = 0; rb < NB; ++rb) av[rb] = la[rb * 64u + lane];
 #pragma unroll
@@ -176,37 +191,50 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
 #pragma unroll
             for (uint32_t r = 0; r < PER; ++r) {
                 const uint32_t q = tid + r * kDenseBlock;
-                if (FULL || q < CF4) lds_a[cur ^ 1u][q] = stage[r];
+                if (FULL || q < STEP_F4) lds[cur ^ 1u][q] = stage[r];
             }
         }
         __syncthreads();
     }
 
-    // f = sum_k y_k^2: this lane holds rows 4 grp + r of every row block.
-    float f = 0.0f;
+    // The upper half hands its partial Y^T to the lower half through LDS
+    // (the staging buffers are free after the loop's last barrier).
+    f4 *red = &lds[0][0];
+    if (half == 1) {
 #pragma unroll
-    for (uint32_t rb = 0; rb < NB; ++rb) {
-        f += acc[rb][0] * acc[rb][0];
-        f += acc[rb][1] * acc[rb][1];
-        f += acc[rb][2] * acc[rb][2];
-        f += acc[rb][3] * acc[rb][3];
+        for (uint32_t rb = 0; rb < NB; ++rb) red[(grp4 * NB + rb) * 64u + lane] = acc[rb];
+    }
+    __syncthreads();
+
+    // f = sum_k y_k^2: this lane holds rows 4 lg + r of every row block.
+    float f = 0.0f;
+    if (half == 0) {
+#pragma unroll
+        for (uint32_t rb = 0; rb < NB; ++rb) {
+            const f4 y = acc[rb] + red[(grp4 * NB + rb) * 64u + lane];
+            f += y[0] * y[0];
+            f += y[1] * y[1];
+            f += y[2] * y[2];
+            f += y[3] * y[3];
+        }
     }
     f += __shfl_xor(f, 16, 64);
     f += __shfl_xor(f, 32, 64);
 
-    const bool improved = valid && (INIT || f < fpi);
+    const bool owner = half == 0 && valid;
+    const bool improved = owner && (INIT || f < fpi);
     uint32_t row = prow;
     float fnew = fpi;
     if (improved) {
         row = INIT ? 0u : 1u - prow;
         fnew = f;
     }
-    if (valid && grp == 0) {
+    if (owner && lg == 0) {
         S.st[i] = improved ? (row | ST_ALIAS) : row;
         if (improved) S.fp[i] = fnew;
     }
-    const unsigned long long key = valid ? gbest_key(fnew, i, row) : ~0ull;
-    generation_commit<kDenseWaves>(S, t, key, (improved && grp == 0) ? 1u : 0u);
+    const unsigned long long key = owner ? gbest_key(fnew, i, row) : ~0ull;
+    generation_commit<kDenseWaves>(S, t, key, (improved && lg == 0) ? 1u : 0u);
 }
 
 template <int NB>
