@@ -89,34 +89,43 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
         prow = st & ST_ROW;
         alias = (st & ST_ALIAS) != 0u;
     }
-    const float *grow_ptr = S.rows;
-    if constexpr (!INIT) {
-        const uint32_t glow = (uint32_t)generation_begin(S, t);
-        const uint32_t gidx = min(glow >> 1, S.n - 1u);
-        grow_ptr = S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.dp;
-    }
     const size_t ioff = (size_t)(valid ? i : 0u) * S.dp;
     const f4 *p4 = reinterpret_cast<const f4 *>(S.rows + prow * S.buf + ioff);
     f4 *x4 = reinterpret_cast<f4 *>(S.rows + (INIT ? 0u : (1u - prow)) * S.buf + ioff);
     // Where the position is read from: the pBest row itself when aliased.
     const f4 *xsrc = alias ? p4 : x4;
-    const f4 *g4 = reinterpret_cast<const f4 *>(grow_ptr);
     const f4 *s4 = reinterpret_cast<const f4 *>(S.s);
 
     // Step m stages K-chunk m (lower half) and K-chunk HALF + m (upper half).
     auto stage_addr = [&](uint32_t m, uint32_t q) -> size_t {
         return (size_t)(q < CF4 ? m : HALF + m) * CF4 + (q % CF4);
     };
+    // Loads that do not depend on gBest go out before the start-of-generation
+    // barrier: the first A step and this lane's first pBest, position, shift.
+    f4 stage0[PER];
 #pragma unroll
     for (uint32_t r = 0; r < PER; ++r) {
         const uint32_t q = tid + r * kDenseBlock;
-        if (FULL || q < STEP_F4) lds[0][q] = a_pack[stage_addr(0, q)];
+        if (FULL || q < STEP_F4) stage0[r] = a_pack[stage_addr(0, q)];
     }
-
-    // Row operands (and shift) of the first chunk this lane selects.
     const uint32_t cbase = 4u * HALF * half;  // first chunk of this wave's half
     const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
     f4 pv = zero4, xv = zero4, gv = zero4, sv = zero4;
+    if (valid && cbase + lg < S.chunks) {
+        sv = s4[cbase + lg];
+        if constexpr (!INIT) {
+            pv = p4[cbase + lg];
+            xv = xsrc[cbase + lg];
+        }
+    }
+
+    const f4 *g4 = reinterpret_cast<const f4 *>(S.rows);
+    if constexpr (!INIT) {
+        const uint32_t glow = (uint32_t)generation_begin(S, t);
+        const uint32_t gidx = min(glow >> 1, S.n - 1u);
+        g4 = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.dp);
+        if (valid && cbase + lg < S.chunks) gv = g4[cbase + lg];
+    }
     auto prefetch = [&](uint32_t c) {
         if (valid && c < S.chunks) {
             sv = s4[c];
@@ -127,7 +136,11 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
             }
         }
     };
-    prefetch(cbase + lg);
+#pragma unroll
+    for (uint32_t r = 0; r < PER; ++r) {
+        const uint32_t q = tid + r * kDenseBlock;
+        if (FULL || q < STEP_F4) lds[0][q] = stage0[r];
+    }
 
     f4 acc[NB];
 #pragma unroll
@@ -233,8 +246,11 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
         S.st[i] = improved ? (row | ST_ALIAS) : row;
         if (improved) S.fp[i] = fnew;
     }
-    const unsigned long long key = owner ? gbest_key(fnew, i, row) : ~0ull;
-    generation_commit<kDenseWaves>(S, t, key, (improved && lg == 0) ? 1u : 0u);
+    // Only the lower halves hold keys; each commits on its own (no barrier).
+    if (half == 0) {
+        const unsigned long long key = owner ? gbest_key(fnew, i, row) : ~0ull;
+        wave_commit(S, t, blockIdx.x * 4u + grp4, key, (improved && lg == 0) ? 1u : 0u);
+    }
 }
 
 template <int NB>

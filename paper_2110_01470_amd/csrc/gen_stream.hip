@@ -41,13 +41,6 @@ __global__ __launch_bounds__(64 * kWaves) void k_stream(SwarmDev S, uint32_t t)
         prow = st & ST_ROW;
         alias = (st & ST_ALIAS) != 0u;
     }
-    // gBest of the previous generation (unused at t == 0).
-    const f4 *g4 = nullptr;
-    if constexpr (!INIT) {
-        const uint32_t glow = (uint32_t)generation_begin(S, t);
-        const uint32_t gidx = min(glow >> 1, S.n - 1u);
-        g4 = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.dp);
-    }
     const size_t ioff = (size_t)(valid ? i : 0u) * S.dp;
     const f4 *p4 = reinterpret_cast<const f4 *>(S.rows + prow * S.buf + ioff);
     // INIT writes the pBest row (row 0); a generation writes the other row.
@@ -58,17 +51,39 @@ __global__ __launch_bounds__(64 * kWaves) void k_stream(SwarmDev S, uint32_t t)
     const f4 *w4 = reinterpret_cast<const f4 *>(S.w);
     const f4 zero = f4{0.f, 0.f, 0.f, 0.f};
 
+    // The first batch of pBest / position loads does not depend on gBest:
+    // issue it before the start-of-generation barrier.
+    f4 pv[kInFlight], xv[kInFlight], gv[kInFlight];
+    if (!INIT && valid) {
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) {
+            const uint32_t c = ln + u * L;
+            if (c < S.chunks) {
+                pv[u] = p4[c];
+                xv[u] = xsrc[c];
+            }
+        }
+    }
+    // gBest of the previous generation (unused at t == 0).
+    const f4 *g4 = nullptr;
+    if constexpr (!INIT) {
+        const uint32_t glow = (uint32_t)generation_begin(S, t);
+        const uint32_t gidx = min(glow >> 1, S.n - 1u);
+        g4 = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.dp);
+    }
+
     float acc = 0.0f;
     if (valid) {
         for (uint32_t c0 = ln; c0 < S.chunks; c0 += kInFlight * L) {
-            f4 pv[kInFlight], xv[kInFlight], gv[kInFlight];
             if constexpr (!INIT) {
 #pragma unroll
                 for (int u = 0; u < kInFlight; ++u) {
                     const uint32_t c = c0 + u * L;
                     if (c < S.chunks) {
-                        pv[u] = p4[c];
-                        xv[u] = xsrc[c];
+                        if (c0 != ln) {  // later batches: rows not issued yet
+                            pv[u] = p4[c];
+                            xv[u] = xsrc[c];
+                        }
                         gv[u] = g4[c];
                     }
                 }

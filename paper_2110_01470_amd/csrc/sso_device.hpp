@@ -200,6 +200,21 @@ __device__ __forceinline__ unsigned long long generation_begin(const SwarmDev &S
     return s_best;
 }
 
+// End of generation t for one wave (no barrier): the wave's minimum key and
+// improvement count folded into sub-slot (wave_id mod 64) of group t % 3.
+__device__ __forceinline__ void wave_commit(const SwarmDev &S, uint32_t t, uint32_t wave_id,
+                                            unsigned long long key, uint32_t improved)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) key = min_u64(key, shfl_xor_u64(key, m));
+    const uint32_t cnt = (uint32_t)__popcll(__ballot(improved != 0u));
+    if ((threadIdx.x & 63u) == 0u) {
+        const uint32_t g = t % kGroups, j = wave_id % kSubSlots;
+        if (key != ~0ull) atomicMin(sub_key(S, g, j), key);
+        if (cnt) atomicAdd(sub_cnt(S, g, j), cnt);
+    }
+}
+
 // End of generation t: minimum key and improvement count over the workgroup's
 // NW waves, folded into sub-slot (blockIdx mod 64) of group t % 3 with one
 // atomic each (thread 0).
