@@ -32,7 +32,7 @@ class Pair:
 
     def __init__(self, kind, n, d, lo=-100.0, hi=100.0, cg=0.4, cp=0.7, cw=0.9, seed=1,
                  s_range=(-50.0, 50.0), order=oracle.ORDER_GPS, engine="auto", lanes=0,
-                 swarm_id=0, trace_cap=0):
+                 swarm_id=0, trace_cap=0, storage="auto"):
         from paper_2110_01470_amd.binding import Swarm
 
         self.kind, self.n, self.d = kind, n, d
@@ -41,7 +41,7 @@ class Pair:
                                 self.a, swarm=swarm_id, order=order)
         self.gpu = Swarm(n, d, kind, lo, hi, cg, cp, cw, seed, self.s, self.w, self.a,
                          swarm_id=swarm_id, order=order, engine=engine, lanes=lanes,
-                         trace_cap=trace_cap)
+                         trace_cap=trace_cap, storage=storage)
         self.orc.init()
         self.band_events = 0
         self.prev_fp64 = self.orc.fp64.copy()

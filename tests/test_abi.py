@@ -46,8 +46,13 @@ def test_workspace_bytes_for_valid_configs():
     nbytes = binding.workspace_bytes(c)
     # two rows of 32 floats per particle, plus fitness, state, shift, trace
     assert nbytes >= 2 * 100 * 32 * 4 + 100 * 8 + 4096 * 12
+    c, keep = cfg(n=65536, d=1000, kind="ripple", w=np.ones(1000, np.float32), storage="f32")
+    f32_bytes = binding.workspace_bytes(c)
+    assert f32_bytes >= 2 * 65536 * 1024 * 4
+    # 24-bit grid indices: 4 variables in 3 words, rows of 768 words for D=1000.
     c, keep = cfg(n=65536, d=1000, kind="ripple", w=np.ones(1000, np.float32))
-    assert binding.workspace_bytes(c) >= 2 * 65536 * 1024 * 4
+    u24_bytes = binding.workspace_bytes(c)
+    assert 2 * 65536 * 768 * 4 <= u24_bytes < f32_bytes
     c, keep = cfg(n=16384, d=256, kind="dense", a=np.eye(256, dtype=np.float32))
     assert binding.workspace_bytes(c) >= 2 * 16384 * 256 * 4 + 256 * 256 * 4
 
@@ -59,6 +64,8 @@ def test_workspace_bytes_for_valid_configs():
     dict(trace_cap=3), dict(kind="ripple"), dict(kind="dense"),
     dict(kind="dense", d=257, a=np.eye(257, dtype=np.float32)),
     dict(engine="resident", n=2000), dict(lo=-3e38, hi=3e38),
+    dict(storage=7), dict(storage="u24", engine="resident"),
+    dict(storage="u24", kind="dense", a=np.eye(30, dtype=np.float32)),
 ])
 def test_invalid_configs_are_rejected(kw):
     c, keep = cfg(**kw)

@@ -84,13 +84,37 @@ def test_sphere_mappings(engine, lanes):
     pair.step(60)
 
 
+@pytest.mark.parametrize("storage", ["u24", "f32"])
 @pytest.mark.parametrize("n,d,order", [(301, 1000, oracle.ORDER_GPS), (67, 1001, oracle.ORDER_GPS),
                                        (45, 37, oracle.ORDER_EQ21), (9, 5, oracle.ORDER_GPS),
                                        (130, 257, oracle.ORDER_EQ21), (1, 1000, oracle.ORDER_GPS)])
-def test_ripple_generations(n, d, order):
+def test_ripple_generations(n, d, order, storage):
     cg, cp, cw = (0.4, 0.7, 0.9) if order == oracle.ORDER_GPS else (0.8, 0.6, 0.3)
-    pair = wl_pair("ripple_n65536_d1000", n=n, d=d, order=order, cg=cg, cp=cp, cw=cw)
+    pair = wl_pair("ripple_n65536_d1000", n=n, d=d, order=order, cg=cg, cp=cp, cw=cw,
+                   engine="stream", storage=storage)
     pair.step(25)
+
+
+@pytest.mark.parametrize("lanes", [8, 16, 32, 64])
+def test_sphere_u24_storage_mappings(lanes):
+    pair = wl_pair("sphere_n100_d30", engine="stream", lanes=lanes, storage="u24")
+    pair.step(40)
+
+
+def test_u24_storage_rejects_off_grid_state():
+    from paper_2110_01470_amd.binding import E_INVAL, SSOError
+
+    pair = wl_pair("ripple_n65536_d1000", n=20, d=9, engine="stream", storage="u24")
+    x, p, fp, t = pair.gpu.state()
+    bad = x.copy()
+    bad[3, 4] = np.nextafter(bad[3, 4], np.float32(np.inf))
+    if np.all(bad == x):
+        bad[3, 4] = np.float32(0.1234567)
+    with pytest.raises(SSOError) as e:
+        pair.gpu.set_state(bad, p, fp, t)
+    assert e.value.code == E_INVAL
+    # The state is unchanged and the run continues in step with the oracle.
+    pair.step(3)
 
 
 @pytest.mark.parametrize("n,d,order", [(130, 256, oracle.ORDER_GPS), (64, 256, oracle.ORDER_EQ21),
@@ -109,9 +133,11 @@ def test_pure_random_search_and_single_source_rules():
         pair.step(10)
 
 
-def test_ripple_n65536_d1000_full_size():
-    """The large ripple workload at full size, as the benchmark launches it."""
-    pair = wl_pair("ripple_n65536_d1000")
+@pytest.mark.parametrize("storage", ["auto", "f32"])
+def test_ripple_n65536_d1000_full_size(storage):
+    """The large ripple workload at full size, as the benchmark launches it
+    (auto storage), and with FP32 rows."""
+    pair = wl_pair("ripple_n65536_d1000", storage=storage)
     pair.compare()
     pair.step(2)
 
@@ -137,8 +163,9 @@ def test_one_generation_from_oracle_states():
         pair.compare()
 
 
-def test_repeatable_and_resumable():
-    kw = dict(n=96, d=200)
+@pytest.mark.parametrize("storage", ["u24", "f32"])
+def test_repeatable_and_resumable(storage):
+    kw = dict(n=96, d=200, storage=storage)
     a = wl_pair("ripple_n65536_d1000", **kw).gpu
     b = wl_pair("ripple_n65536_d1000", **kw).gpu
     a.run(30)
