@@ -59,12 +59,25 @@ typedef enum {
 typedef enum { SSO_ORDER_GPS = 0, SSO_ORDER_EQ21 = 1 } sso_order;
 
 /* Engines.  AUTO picks RESIDENT when the whole swarm fits one workgroup's
- * registers, else STREAM.  Every engine gives bit-identical positions. */
+ * registers, else STREAM.  RESIDENT and STREAM with the same lanes per
+ * particle sum each fitness in the same order and give bit-identical runs;
+ * another lanes setting sums in another order, so a pBest or gBest decision
+ * between two fitness values a few FP32 ulps apart may go the other way. */
 typedef enum {
     SSO_ENGINE_AUTO     = 0,
     SSO_ENGINE_STREAM   = 1, /* one fused kernel per generation                 */
     SSO_ENGINE_RESIDENT = 2  /* one workgroup keeps the swarm on chip and loops */
 } sso_engine;
+
+/* Row storage of positions and pBests.  Every position the method produces
+ * is a point of the draw grid lo + u (hi - lo) 2^-24 with an integer
+ * 0 <= u < 2^24 (values are only drawn that way, Eq. (2.1) and kernel (I), or
+ * copied), so the STREAM engine can keep the 24-bit u instead of the FP32
+ * value: 9 bytes move per variable and generation instead of 12, with
+ * bit-identical positions.  AUTO picks U24 for the STREAM engine on the
+ * separable objectives and F32 otherwise.  With U24, sso_set_state accepts
+ * only positions on that grid. */
+typedef enum { SSO_STORAGE_AUTO = 0, SSO_STORAGE_F32 = 1, SSO_STORAGE_U24 = 2 } sso_storage;
 
 typedef struct {
     uint32_t n;          /* Nsol, particles, >= 1, < 2^31                         */
@@ -78,6 +91,7 @@ typedef struct {
     int32_t  kind;       /* sso_objective                                         */
     int32_t  order;      /* sso_order                                             */
     int32_t  engine;     /* sso_engine                                            */
+    int32_t  storage;    /* sso_storage                                           */
     uint32_t lanes;      /* STREAM engine lanes per particle: 0 = auto, else a
                             power of two in [8, 64]                               */
     uint32_t trace_cap;  /* generations of (fG, gidx, improved) kept on device;
@@ -118,7 +132,9 @@ int sso_get_state(sso_ctx *ctx, float *x, float *p, float *fp, uint64_t *t);
 
 /* Replace the state with host arrays x, p [n*d], fp [n] and the generation
  * count t; gBest becomes the lowest-index argmin of fp.  Used for
- * checkpoint/resume and for parity checks from a given state.  Synchronises. */
+ * checkpoint/resume and for parity checks from a given state.  Synchronises.
+ * With U24 storage a value off the draw grid returns SSO_E_INVAL and leaves
+ * the state unchanged. */
 int sso_set_state(sso_ctx *ctx, const float *x, const float *p, const float *fp,
                   uint64_t t);
 

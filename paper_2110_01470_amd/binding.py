@@ -18,6 +18,7 @@ OK, E_INVAL, E_NOMEM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5
 OBJ = {"sphere": 0, "ripple": 1, "dense": 2}
 ORDER_GPS, ORDER_EQ21 = 0, 1
 ENGINE = {"auto": 0, "stream": 1, "resident": 2}
+STORAGE = {"auto": 0, "f32": 1, "u24": 2}
 
 
 class SSOError(RuntimeError):
@@ -41,6 +42,7 @@ class Config(ctypes.Structure):
         ("kind", ctypes.c_int32),
         ("order", ctypes.c_int32),
         ("engine", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
         ("lanes", ctypes.c_uint32),
         ("trace_cap", ctypes.c_uint32),
         ("s", ctypes.c_void_p),
@@ -93,12 +95,13 @@ def _f32(a):
 
 
 def make_config(n, d, kind, lo, hi, cg, cp, cw, seed, s, w=None, a=None, swarm_id=0,
-                order=ORDER_GPS, engine="auto", lanes=0, trace_cap=0):
+                order=ORDER_GPS, engine="auto", lanes=0, trace_cap=0, storage="auto"):
     """Returns (Config, keepalive) with host arrays pinned in `keepalive`."""
     s, w, a = _f32(s), _f32(w), _f32(a)
     cfg = Config(n=n, d=d, lo=lo, hi=hi, cg=cg, cp=cp, cw=cw, seed=seed, swarm_id=swarm_id,
                  kind=OBJ[kind] if isinstance(kind, str) else kind, order=order,
-                 engine=ENGINE[engine] if isinstance(engine, str) else engine, lanes=lanes,
+                 engine=ENGINE[engine] if isinstance(engine, str) else engine,
+                 storage=STORAGE[storage] if isinstance(storage, str) else storage, lanes=lanes,
                  trace_cap=trace_cap, s=s.ctypes.data if s is not None else None,
                  w=w.ctypes.data if w is not None else None,
                  a=a.ctypes.data if a is not None else None)
@@ -118,14 +121,14 @@ class Swarm:
     sso_get_best and the state, trace and RNG hooks."""
 
     def __init__(self, n, d, kind, lo, hi, cg, cp, cw, seed, s, w=None, a=None, swarm_id=0,
-                 order=ORDER_GPS, engine="auto", lanes=0, trace_cap=0, device="cuda",
-                 stream=None):
+                 order=ORDER_GPS, engine="auto", lanes=0, trace_cap=0, storage="auto",
+                 device="cuda", stream=None):
         import torch
 
         self._lib = load()
         self.n, self.d = n, d
         self._cfg, self._keep = make_config(n, d, kind, lo, hi, cg, cp, cw, seed, s, w, a,
-                                            swarm_id, order, engine, lanes, trace_cap)
+                                            swarm_id, order, engine, lanes, trace_cap, storage)
         nbytes = workspace_bytes(self._cfg)
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

@@ -32,6 +32,9 @@ namespace sso {
 
 typedef f4 floatx4;
 
+#ifndef SSO_DENSE_DIRECT_A
+#define SSO_DENSE_DIRECT_A 0
+#endif
 constexpr int kDenseWaves = 8;
 constexpr int kDenseBlock = 64 * kDenseWaves;
 
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
         prow = st & ST_ROW;
         alias = (st & ST_ALIAS) != 0u;
     }
-    const size_t ioff = (size_t)(valid ? i : 0u) * S.dp;
+    const size_t ioff = (size_t)(valid ? i : 0u) * S.stride;
     const f4 *p4 = reinterpret_cast<const f4 *>(S.rows + prow * S.buf + ioff);
     f4 *x4 = reinterpret_cast<f4 *>(S.rows + (INIT ? 0u : (1u - prow)) * S.buf + ioff);
     // Where the position is read from: the pBest row itself when aliased.
@@ -103,11 +106,20 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     // Loads that do not depend on gBest go out before the start-of-generation
     // barrier: the first A step and this lane's first pBest, position, shift.
     f4 stage0[PER];
+#if SSO_DENSE_DIRECT_A
+    // Each wave reads its own A operands straight from global memory (A is
+    // L2-resident), one step ahead; no staging and no barrier in the loop.
+    const uint32_t mbase = HALF * half;  // this wave's first K-chunk
+    f4 av[NB];
+#pragma unroll
+    for (uint32_t rb = 0; rb < NB; ++rb) av[rb] = a_pack[(size_t)mbase * CF4 + rb * 64u + lane];
+#else
 #pragma unroll
     for (uint32_t r = 0; r < PER; ++r) {
         const uint32_t q = tid + r * kDenseBlock;
         if (FULL || q < STEP_F4) stage0[r] = a_pack[stage_addr(0, q)];
     }
+#endif
     const uint32_t cbase = 4u * HALF * half;  // first chunk of this wave's half
     const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
     f4 pv = zero4, xv = zero4, gv = zero4, sv = zero4;
@@ -121,9 +133,9 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
 
     const f4 *g4 = reinterpret_cast<const f4 *>(S.rows);
     if constexpr (!INIT) {
-        const uint32_t glow = (uint32_t)generation_begin(S, t);
+        const uint32_t glow = (uint32_t)generation_begin(S, t, blockIdx.x);
         const uint32_t gidx = min(glow >> 1, S.n - 1u);
-        g4 = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.dp);
+        g4 = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.stride);
         if (valid && cbase + lg < S.chunks) gv = g4[cbase + lg];
     }
     auto prefetch = [&](uint32_t c) {
@@ -136,11 +148,13 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
             }
         }
     };
+#if !SSO_DENSE_DIRECT_A
 #pragma unroll
     for (uint32_t r = 0; r < PER; ++r) {
         const uint32_t q = tid + r * kDenseBlock;
         if (FULL || q < STEP_F4) lds[0][q] = stage0[r];
     }
+#endif
 
     f4 acc[NB];
 #pragma unroll
@@ -172,6 +186,15 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
             dv.z = (j0 + 2 < S.d) ? xn.z - sv.z : 0.f;
             dv.w = (j0 + 3 < S.d) ? xn.w - sv.w : 0.f;
         }
+#if SSO_DENSE_DIRECT_A
+        f4 avn[NB];
+        if (more) {
+            prefetch(c + 4u);
+#pragma unroll
+            for (uint32_t rb = 0; rb < NB; ++rb)
+                avn[rb] = a_pack[(size_t)(mbase + m + 1) * CF4 + rb * 64u + lane];
+        }
+#else
         f4 stage[PER];
         if (more) {
             prefetch(c + 4u);
@@ -181,13 +204,13 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
                 if (FULL || q < STEP_F4) stage[r] = a_pack[stage_addr(m + 1, q)];
             }
         }
-
-        // Y^T += A[:, chunk] * D^T[chunk, :] for every row block; the
-        // e-outer order keeps consecutive MFMAs on different accumulators.
         const f4 *la = lds[cur] + half * CF4;
         f4 av[NB];
 #pragma unroll
         for (uint32_t rb = 0; rb < NB; ++rb) av[rb] = la[rb * 64u + lane];
+#endif
+        // Y^T += A[:, chunk] * D^T[chunk, :] for every row block; the
+        // e-outer order keeps consecutive MFMAs on different accumulators.
 #pragma unroll
         for (uint32_t rb = 0; rb < NB; ++rb)
             acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb][0], dv.x, acc[rb], 0, 0, 0);
@@ -200,6 +223,13 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
 #pragma unroll
         for (uint32_t rb = 0; rb < NB; ++rb)
             acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb][3], dv.w, acc[rb], 0, 0, 0);
+#if SSO_DENSE_DIRECT_A
+        if (more) {
+#pragma unroll
+            for (uint32_t rb = 0; rb < NB; ++rb) av[rb] = avn[rb];
+        }
+        (void)cur;
+#else
         if (more) {
 #pragma unroll
             for (uint32_t r = 0; r < PER; ++r) {
@@ -208,7 +238,11 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
             }
         }
         __syncthreads();
+#endif
     }
+#if SSO_DENSE_DIRECT_A
+    __syncthreads();
+#endif
 
     // The upper half hands its partial Y^T to the lower half through LDS
     // (the staging buffers are free after the loop's last barrier).

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, ui
         if (owns) {
             // An aliased position is the pBest row itself; selecting the row
             // pointer (not the loaded value) keeps both loads in registers.
-            const size_t off = (size_t)i * S.dp;
+            const size_t off = (size_t)i * S.stride;
             const float *prow_ptr = S.rows + prow * S.buf + off;
             const float *xrow_ptr = (st & ST_ALIAS) ? prow_ptr : S.rows + (1u - prow) * S.buf + off;
             pv = reinterpret_cast<const f4 *>(prow_ptr)[c];
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, ui
         const uint32_t glow = (uint32_t)gk;
         const uint32_t gidx = min(glow >> 1, S.n - 1u);
         const f4 *grow = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf +
-                                                      (size_t)gidx * S.dp);
+                                                      (size_t)gidx * S.stride);
         for (uint32_t q = threadIdx.x; q < S.chunks; q += blockDim.x) s_g[q] = grow[q];
     }
     __syncthreads();
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, ui
 
     // Write back: pBest in row 0, position in row 1, no aliasing.
     if (valid) {
-        const size_t off = (size_t)i * S.dp;
+        const size_t off = (size_t)i * S.stride;
         if (owns) {
             reinterpret_cast<f4 *>(S.rows + off)[c] = pv;
             reinterpret_cast<f4 *>(S.rows + S.buf + off)[c] = xv;

@@ -21,6 +21,7 @@ struct sso_ctx {
     SwarmDev S;
     hipStream_t stream;
     int engine;        // resolved engine
+    int storage;       // resolved row storage (STORE_F32 / STORE_U24)
     uint32_t lanes;    // STREAM lanes per particle
     uint64_t t;        // generations done
     uint64_t trace_base;
@@ -40,16 +41,22 @@ uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 
 struct Layout {
     size_t rows, fp, st, s, w, a, keys, cnt, sub, total;
-    uint32_t dp, trace_cap;
+    uint32_t dp, stride, trace_cap;
+    int engine, storage;
 };
+
+// Engine and storage a valid configuration resolves to.
+void resolve(const sso_config &c, int *engine, int *storage);
 
 Layout make_layout(const sso_config &c)
 {
     Layout L{};
+    resolve(c, &L.engine, &L.storage);
     L.dp = round_up(c.d, kRowAlign);
+    L.stride = L.storage == STORE_U24 ? round_up(3 * ((c.d + 3) / 4), kRowAlign) : L.dp;
     L.trace_cap = c.trace_cap ? c.trace_cap : kDefaultTraceCap;
     size_t off = 0;
-    L.rows = off; off += align256((size_t)2 * c.n * L.dp * sizeof(float));
+    L.rows = off; off += align256((size_t)2 * c.n * L.stride * sizeof(uint32_t));
     L.fp = off;   off += align256((size_t)c.n * sizeof(float));
     L.st = off;   off += align256((size_t)c.n * sizeof(uint32_t));
     L.s = off;    off += align256((size_t)L.dp * sizeof(float));
@@ -64,11 +71,28 @@ Layout make_layout(const sso_config &c)
 
 uint64_t threshold(double c) { return (uint64_t)std::ceil(c * 4294967296.0); }
 
-uint32_t stream_lanes(uint32_t d)
+bool resident_possible(const sso_config &c) { return resident_fits(c.n, c.d, c.kind); }
+
+void resolve(const sso_config &c, int *engine, int *storage)
+{
+    int e = c.engine;
+    if (c.kind == SSO_OBJ_DENSE) e = SSO_ENGINE_STREAM;
+    if (e == SSO_ENGINE_AUTO) e = resident_possible(c) ? SSO_ENGINE_RESIDENT : SSO_ENGINE_STREAM;
+    *engine = e;
+    const bool packable = e == SSO_ENGINE_STREAM && c.kind != SSO_OBJ_DENSE;
+    *storage = (c.storage == SSO_STORAGE_F32 || !packable) ? STORE_F32 : STORE_U24;
+}
+
+// Lanes per particle for the STREAM engine: the chunk count rounded up to a
+// power of two, at least 8, at most 32 with 24-bit rows and 64 with FP32 rows
+// (measured on the ripple workload with D=1000: U24 131.9 us at 32 lanes vs
+// 135.1 at 64; F32 160.2 us at 64 vs 172.1 at 32).
+uint32_t stream_lanes(uint32_t d, int storage)
 {
     const uint32_t chunks = (d + 3) / 4;
+    const uint32_t cap = storage == STORE_U24 ? 32u : 64u;
     uint32_t L = 8;
-    while (L < chunks && L < 64) L <<= 1;
+    while (L < chunks && L < cap) L <<= 1;
     return L;
 }
 
@@ -107,6 +131,13 @@ int validate(const sso_config *c, std::string *why)
         return bad(SSO_E_INVAL, "fresh interval must hold more than 2^24 words (1 - last threshold > 2^-8)");
     if (c->engine == SSO_ENGINE_RESIDENT && !resident_fits(c->n, c->d, c->kind))
         return bad(SSO_E_UNSUPPORTED, "swarm does not fit the resident engine (one workgroup, separable objective)");
+    if (c->storage < SSO_STORAGE_AUTO || c->storage > SSO_STORAGE_U24) return bad(SSO_E_INVAL, "unknown storage");
+    if (c->storage == SSO_STORAGE_U24) {
+        int e, st;
+        resolve(*c, &e, &st);
+        if (st != STORE_U24)
+            return bad(SSO_E_UNSUPPORTED, "24-bit storage needs the STREAM engine and a separable objective");
+    }
     return SSO_OK;
 }
 
@@ -139,6 +170,66 @@ float from_orderable(uint32_t o)
     float f;
     std::memcpy(&f, &b, 4);
     return f;
+}
+
+// Row conversion between FP32 values and the storage format.  A U24 row holds
+// the grid index u of every value, value = fma(u, span 2^-24, lo) rounded
+// once to FP32, four indices per three 32-bit words (sso_layout.hpp).
+float grid_value(const SwarmDev &S, uint32_t u) { return std::fmaf((float)(int32_t)u, S.span24, S.lo); }
+
+void row_to_values(const SwarmDev &S, const uint32_t *row, float *out)
+{
+    if (S.storage == STORE_F32) {
+        std::memcpy(out, row, sizeof(float) * S.d);
+        return;
+    }
+    for (uint32_t j = 0; j < S.d; ++j) {
+        const uint32_t *w = row + 3 * (j / 4);
+        uint32_t u = 0;
+        switch (j % 4) {
+        case 0: u = w[0] & 0xFFFFFFu; break;
+        case 1: u = (w[0] >> 24) | ((w[1] & 0xFFFFu) << 8); break;
+        case 2: u = (w[1] >> 16) | ((w[2] & 0xFFu) << 16); break;
+        default: u = w[2] >> 8; break;
+        }
+        out[j] = grid_value(S, u);
+    }
+}
+
+bool same_bits(float a, float b) { return std::memcmp(&a, &b, sizeof a) == 0; }
+
+// Grid index of x, or false when x is not a grid point.
+bool grid_index(const SwarmDev &S, float x, uint32_t *u)
+{
+    if (!std::isfinite(x)) return false;
+    const double guess = std::nearbyint(((double)x - (double)S.lo) / (double)S.span24);
+    for (double cand : {guess, guess - 1.0, guess + 1.0}) {
+        if (cand < 0.0 || cand >= 16777216.0) continue;
+        if (same_bits(grid_value(S, (uint32_t)cand), x)) {
+            *u = (uint32_t)cand;
+            return true;
+        }
+    }
+    return false;
+}
+
+bool values_to_row(const SwarmDev &S, const float *in, uint32_t *row)
+{
+    if (S.storage == STORE_F32) {
+        std::memcpy(row, in, sizeof(float) * S.d);
+        return true;
+    }
+    for (uint32_t c = 0; c < S.chunks; ++c) {
+        uint32_t u[4] = {0, 0, 0, 0};
+        for (uint32_t e = 0; e < 4; ++e) {
+            const uint32_t j = 4 * c + e;
+            if (j < S.d && !grid_index(S, in[j], &u[e])) return false;
+        }
+        row[3 * c + 0] = u[0] | (u[1] << 24);
+        row[3 * c + 1] = (u[1] >> 8) | (u[2] << 16);
+        row[3 * c + 2] = (u[2] >> 16) | (u[3] << 8);
+    }
+    return true;
 }
 
 // gBest key and improvement count of generation t, from its sub-slot group
@@ -242,12 +333,10 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
     ctx->stream = (hipStream_t)stream;
     ctx->t = 0;
     ctx->trace_base = 0;
-    int engine = cfg->engine;
-    if (cfg->kind == SSO_OBJ_DENSE) engine = SSO_ENGINE_STREAM;
-    if (engine == SSO_ENGINE_AUTO)
-        engine = resident_fits(cfg->n, cfg->d, cfg->kind) ? SSO_ENGINE_RESIDENT : SSO_ENGINE_STREAM;
+    const int engine = L.engine;
     ctx->engine = engine;
-    ctx->lanes = (engine == SSO_ENGINE_STREAM && cfg->lanes) ? cfg->lanes : stream_lanes(cfg->d);
+    ctx->storage = L.storage;
+    ctx->lanes = (engine == SSO_ENGINE_STREAM && cfg->lanes) ? cfg->lanes : stream_lanes(cfg->d, L.storage);
 
     char *base = (char *)ws;
     SwarmDev &S = ctx->S;
@@ -260,10 +349,12 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
     S.keys = (unsigned long long *)(base + L.keys);
     S.cnt = (uint32_t *)(base + L.cnt);
     S.sub = (unsigned long long *)(base + L.sub);
-    S.buf = (uint64_t)cfg->n * L.dp;
+    S.buf = (uint64_t)cfg->n * L.stride;
     S.n = cfg->n;
     S.d = cfg->d;
     S.dp = L.dp;
+    S.stride = L.stride;
+    S.storage = L.storage;
     S.chunks = (cfg->d + 3) / 4;
     S.trace_cap = L.trace_cap;
     const bool gps = cfg->order == SSO_ORDER_GPS;
@@ -282,6 +373,8 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
     S.swarm = cfg->swarm_id;
     S.kind = cfg->kind;
     S.order = cfg->order;
+    S.nsub = kSubSlots;
+    S.lanes = ctx->lanes;
 
     std::vector<float> pad(L.dp, 0.0f);
     std::memcpy(pad.data(), cfg->s, sizeof(float) * cfg->d);
@@ -346,9 +439,12 @@ int sso_get_best(sso_ctx *ctx, float *g_out, float *f_out, uint32_t *idx_out, ui
         ctx->err = "no gBest recorded for the current generation";
         return SSO_E_STATE;
     }
-    if (g_out)
-        HIP_TRY(&ctx->err, hipMemcpy(g_out, S.rows + row * S.buf + (size_t)gidx * S.dp, sizeof(float) * S.d,
-                                     hipMemcpyDeviceToHost));
+    if (g_out) {
+        std::vector<uint32_t> words(S.stride);
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(S.rows) + row * S.buf + (size_t)gidx * S.stride;
+        HIP_TRY(&ctx->err, hipMemcpy(words.data(), src, sizeof(uint32_t) * S.stride, hipMemcpyDeviceToHost));
+        row_to_values(S, words.data(), g_out);
+    }
     if (f_out) *f_out = from_orderable((uint32_t)(key >> 32));
     if (idx_out) *idx_out = gidx;
     if (gen_out) *gen_out = ctx->t;
@@ -361,16 +457,16 @@ int sso_get_state(sso_ctx *ctx, float *x, float *p, float *fp, uint64_t *t)
     const SwarmDev &S = ctx->S;
     HIP_TRY(&ctx->err, hipStreamSynchronize(ctx->stream));
     if (x || p) {
-        std::vector<float> rows((size_t)2 * S.buf);
+        std::vector<uint32_t> rows((size_t)2 * S.buf);
         std::vector<uint32_t> st(S.n);
-        HIP_TRY(&ctx->err, hipMemcpy(rows.data(), S.rows, sizeof(float) * rows.size(), hipMemcpyDeviceToHost));
+        HIP_TRY(&ctx->err, hipMemcpy(rows.data(), S.rows, sizeof(uint32_t) * rows.size(), hipMemcpyDeviceToHost));
         HIP_TRY(&ctx->err, hipMemcpy(st.data(), S.st, sizeof(uint32_t) * S.n, hipMemcpyDeviceToHost));
         for (uint32_t i = 0; i < S.n; ++i) {
             const uint32_t prow = st[i] & ST_ROW;
-            const float *pr = rows.data() + prow * S.buf + (size_t)i * S.dp;
-            const float *xr = (st[i] & ST_ALIAS) ? pr : rows.data() + (1u - prow) * S.buf + (size_t)i * S.dp;
-            if (p) std::memcpy(p + (size_t)i * S.d, pr, sizeof(float) * S.d);
-            if (x) std::memcpy(x + (size_t)i * S.d, xr, sizeof(float) * S.d);
+            const uint32_t *pr = rows.data() + prow * S.buf + (size_t)i * S.stride;
+            const uint32_t *xr = (st[i] & ST_ALIAS) ? pr : rows.data() + (1u - prow) * S.buf + (size_t)i * S.stride;
+            if (p) row_to_values(S, pr, p + (size_t)i * S.d);
+            if (x) row_to_values(S, xr, x + (size_t)i * S.d);
         }
     }
     if (fp) HIP_TRY(&ctx->err, hipMemcpy(fp, S.fp, sizeof(float) * S.n, hipMemcpyDeviceToHost));
@@ -390,10 +486,13 @@ int sso_set_state(sso_ctx *ctx, const float *x, const float *p, const float *fp,
         return SSO_E_UNSUPPORTED;
     }
     const SwarmDev &S = ctx->S;
-    std::vector<float> rows((size_t)2 * S.buf, 0.0f);
+    std::vector<uint32_t> rows((size_t)2 * S.buf, 0u);
     for (uint32_t i = 0; i < S.n; ++i) {
-        std::memcpy(rows.data() + (size_t)i * S.dp, p + (size_t)i * S.d, sizeof(float) * S.d);
-        std::memcpy(rows.data() + S.buf + (size_t)i * S.dp, x + (size_t)i * S.d, sizeof(float) * S.d);
+        if (!values_to_row(S, p + (size_t)i * S.d, rows.data() + (size_t)i * S.stride) ||
+            !values_to_row(S, x + (size_t)i * S.d, rows.data() + S.buf + (size_t)i * S.stride)) {
+            ctx->err = "a position is not on the 24-bit draw grid of [lo, hi] (use F32 storage)";
+            return SSO_E_INVAL;
+        }
     }
     std::vector<uint32_t> st(S.n, 0u);
     // gBest of the imported state: lowest-index argmin (pBests sit in row 0).
@@ -405,7 +504,7 @@ int sso_set_state(sso_ctx *ctx, const float *x, const float *p, const float *fp,
     }
     const uint32_t zero = 0;
     HIP_TRY(&ctx->err, hipStreamSynchronize(ctx->stream));
-    HIP_TRY(&ctx->err, hipMemcpy(S.rows, rows.data(), sizeof(float) * rows.size(), hipMemcpyHostToDevice));
+    HIP_TRY(&ctx->err, hipMemcpy(S.rows, rows.data(), sizeof(uint32_t) * rows.size(), hipMemcpyHostToDevice));
     HIP_TRY(&ctx->err, hipMemcpy(S.st, st.data(), sizeof(uint32_t) * S.n, hipMemcpyHostToDevice));
     HIP_TRY(&ctx->err, hipMemcpy(S.fp, fp, sizeof(float) * S.n, hipMemcpyHostToDevice));
     const int e = launch_fill_trace(S, ctx->stream);

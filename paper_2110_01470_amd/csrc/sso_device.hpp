@@ -91,6 +91,77 @@ __device__ __forceinline__ f4 select4(const SwarmDev &S, uint4 k, f4 g, f4 p, f4
 }
 
 // ---------------------------------------------------------------------------
+// Row storage policies for the generation kernels (see sso_layout.hpp).
+// T is the in-register form of one chunk of 4 variables; value() gives the
+// FP32 positions the objective is evaluated on.
+// ---------------------------------------------------------------------------
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+
+struct U24x4 {
+    uint32_t w0, w1, w2;
+};
+
+struct StoreF32 {
+    using T = f4;
+    static constexpr bool kPacked = false;
+    __device__ static T load(const uint32_t *row, uint32_t c)
+    {
+        return reinterpret_cast<const f4 *>(row)[c];
+    }
+    __device__ static void store(uint32_t *row, uint32_t c, T v) { reinterpret_cast<f4 *>(row)[c] = v; }
+    __device__ static T init(const SwarmDev &S, uint4 k) { return init4(S, k); }
+    template <bool EQ21>
+    __device__ static T select(const SwarmDev &S, uint4 k, T g, T p, T x)
+    {
+        return select4<EQ21>(S, k, g, p, x);
+    }
+    __device__ static f4 value(const SwarmDev &, T v) { return v; }
+};
+
+template <bool EQ21>
+__device__ __forceinline__ uint32_t select_u(const SwarmDev &S, uint32_t k, uint32_t g, uint32_t p,
+                                             uint32_t x)
+{
+    const uint32_t first = EQ21 ? x : g;
+    const uint32_t third = EQ21 ? g : x;
+    uint32_t v = __umulhi(k - S.th2, S.r);  // fresh grid index
+    v = (k < S.th2) ? third : v;
+    v = (k < S.th1) ? p : v;
+    v = (k < S.th0) ? first : v;
+    return v;
+}
+
+struct StoreU24 {
+    using T = u4v;
+    static constexpr bool kPacked = true;
+    __device__ static T load(const uint32_t *row, uint32_t c)
+    {
+        const U24x4 q = reinterpret_cast<const U24x4 *>(row)[c];
+        return T{q.w0 & 0xFFFFFFu, __builtin_amdgcn_alignbit(q.w1, q.w0, 24) & 0xFFFFFFu,
+                 __builtin_amdgcn_alignbit(q.w2, q.w1, 16) & 0xFFFFFFu, q.w2 >> 8};
+    }
+    __device__ static void store(uint32_t *row, uint32_t c, T u)
+    {
+        reinterpret_cast<U24x4 *>(row)[c] =
+            U24x4{u.x | (u.y << 24), (u.y >> 8) | (u.z << 16), (u.z >> 16) | (u.w << 8)};
+    }
+    __device__ static T init(const SwarmDev &, uint4 k)
+    {
+        return T{k.x >> 8, k.y >> 8, k.z >> 8, k.w >> 8};
+    }
+    template <bool EQ21>
+    __device__ static T select(const SwarmDev &S, uint4 k, T g, T p, T x)
+    {
+        return T{select_u<EQ21>(S, k.x, g.x, p.x, x.x), select_u<EQ21>(S, k.y, g.y, p.y, x.y),
+                 select_u<EQ21>(S, k.z, g.z, p.z, x.z), select_u<EQ21>(S, k.w, g.w, p.w, x.w)};
+    }
+    __device__ static f4 value(const SwarmDev &S, T u)
+    {
+        return f4{draw24(S, u.x), draw24(S, u.y), draw24(S, u.z), draw24(S, u.w)};
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Separable objectives: FP32 terms of four variables starting at column j0;
 // columns >= d are padding and contribute nothing.
 //
@@ -124,6 +195,17 @@ __device__ __forceinline__ float terms4(f4 x, f4 s, f4 w, uint32_t j0, uint32_t 
     t1 = (j0 + 1 < d) ? t1 : 0.0f;
     t2 = (j0 + 2 < d) ? t2 : 0.0f;
     t3 = (j0 + 3 < d) ? t3 : 0.0f;
+    return (t0 + t1) + (t2 + t3);
+}
+
+// All four columns real (d is a multiple of 4): no padding masks.
+template <int KIND>
+__device__ __forceinline__ float terms4_full(f4 x, f4 s, f4 w)
+{
+    const float t0 = term1<KIND>(x.x, s.x, w.x);
+    const float t1 = term1<KIND>(x.y, s.y, w.y);
+    const float t2 = term1<KIND>(x.z, s.z, w.z);
+    const float t3 = term1<KIND>(x.w, s.w, w.w);
     return (t0 + t1) + (t2 + t3);
 }
 
@@ -170,21 +252,23 @@ __device__ __forceinline__ uint32_t *sub_cnt(const SwarmDev &S, uint32_t group, 
 
 // Start of generation t >= 1 (all threads of the workgroup call it; it holds
 // one barrier).  Wave 0 reduces the sub-slots of generation t - 1 (one load
-// per lane, kSubSlots == 64) and shares the gBest key through LDS.
-// Workgroup 0 also records that key and the improvement count in the trace
-// ring and clears the group generation t + 1 will commit into.
-__device__ __forceinline__ unsigned long long generation_begin(const SwarmDev &S, uint32_t t)
+// per lane, nsub <= 64) and shares the gBest key through LDS.  Workgroup 0
+// of the swarm (blk == 0) also records that key and the improvement count in
+// the trace ring and clears the group generation t + 1 will commit into.
+__device__ __forceinline__ unsigned long long generation_begin(const SwarmDev &S, uint32_t t,
+                                                               uint32_t blk)
 {
     __shared__ unsigned long long s_best;
     const uint32_t lane = threadIdx.x & 63u;
     if (threadIdx.x < 64u) {
         const uint32_t g = (t - 1u) % kGroups;
-        unsigned long long k = *sub_key(S, g, lane);
+        const bool used = lane < S.nsub;
+        unsigned long long k = used ? *sub_key(S, g, lane) : ~0ull;
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) k = min_u64(k, shfl_xor_u64(k, m));
         if (lane == 0) s_best = k;
-        if (blockIdx.x == 0) {
-            uint32_t c = *sub_cnt(S, g, lane);
+        if (blk == 0) {
+            uint32_t c = used ? *sub_cnt(S, g, lane) : 0u;
 #pragma unroll
             for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m, 64);
             if (lane == 0) {
@@ -192,8 +276,10 @@ __device__ __forceinline__ unsigned long long generation_begin(const SwarmDev &S
                 S.cnt[(t - 1u) % S.trace_cap] = c;
             }
             const uint32_t gn = (t + 1u) % kGroups;
-            *sub_key(S, gn, lane) = ~0ull;
-            *sub_cnt(S, gn, lane) = 0u;
+            if (used) {
+                *sub_key(S, gn, lane) = ~0ull;
+                *sub_cnt(S, gn, lane) = 0u;
+            }
         }
     }
     __syncthreads();
@@ -201,7 +287,7 @@ __device__ __forceinline__ unsigned long long generation_begin(const SwarmDev &S
 }
 
 // End of generation t for one wave (no barrier): the wave's minimum key and
-// improvement count folded into sub-slot (wave_id mod 64) of group t % 3.
+// improvement count folded into sub-slot (wave_id mod nsub) of group t % 3.
 __device__ __forceinline__ void wave_commit(const SwarmDev &S, uint32_t t, uint32_t wave_id,
                                             unsigned long long key, uint32_t improved)
 {
@@ -209,17 +295,17 @@ __device__ __forceinline__ void wave_commit(const SwarmDev &S, uint32_t t, uint3
     for (int m = 32; m >= 1; m >>= 1) key = min_u64(key, shfl_xor_u64(key, m));
     const uint32_t cnt = (uint32_t)__popcll(__ballot(improved != 0u));
     if ((threadIdx.x & 63u) == 0u) {
-        const uint32_t g = t % kGroups, j = wave_id % kSubSlots;
+        const uint32_t g = t % kGroups, j = wave_id & (S.nsub - 1u);
         if (key != ~0ull) atomicMin(sub_key(S, g, j), key);
         if (cnt) atomicAdd(sub_cnt(S, g, j), cnt);
     }
 }
 
 // End of generation t: minimum key and improvement count over the workgroup's
-// NW waves, folded into sub-slot (blockIdx mod 64) of group t % 3 with one
-// atomic each (thread 0).
+// NW waves, folded into sub-slot (blk mod nsub) of group t % 3 with one atomic
+// each (thread 0).
 template <int NW>
-__device__ __forceinline__ void generation_commit(const SwarmDev &S, uint32_t t,
+__device__ __forceinline__ void generation_commit(const SwarmDev &S, uint32_t t, uint32_t blk,
                                                   unsigned long long key, uint32_t improved)
 {
     __shared__ unsigned long long s_key[NW];
@@ -241,7 +327,7 @@ __device__ __forceinline__ void generation_commit(const SwarmDev &S, uint32_t t,
             k = min_u64(k, s_key[w]);
             c += s_cnt[w];
         }
-        const uint32_t g = t % kGroups, j = blockIdx.x % kSubSlots;
+        const uint32_t g = t % kGroups, j = blk & (S.nsub - 1u);
         if (k != ~0ull) atomicMin(sub_key(S, g, j), k);
         if (c) atomicAdd(sub_cnt(S, g, j), c);
     }

@@ -20,6 +20,14 @@
 namespace sso {
 
 enum { OBJ_SPHERE = 0, OBJ_RIPPLE = 1, OBJ_DENSE = 2 };
+
+// Row storage.  F32: dp floats per row, a float4 per chunk of 4 variables.
+// U24: every position is a point of the draw grid lo + u span 2^-24 with a
+// 24-bit u (positions are only ever drawn that way or copied), so a row can
+// hold the indices u: the 4 of a chunk packed into 3 32-bit words,
+//   w0 = u0 | u1 << 24,  w1 = u1 >> 8 | u2 << 16,  w2 = u2 >> 16 | u3 << 8,
+// which moves 9 bytes per variable and generation instead of 12.
+enum { STORE_F32 = 0, STORE_U24 = 1 };
 enum : uint32_t { ST_ROW = 1u, ST_ALIAS = 2u };
 
 constexpr uint32_t kRowAlign = 32;      // floats per row alignment unit (128 B)
@@ -31,14 +39,15 @@ constexpr uint32_t kDenseMaxD = 256;    // dense kernel limit on d
 // 64-bit words (256 B) apart so the atomics of different workgroups do not
 // serialise on one line.  Groups rotate over kGroups generations: generation
 // t commits into group t % 3, reduces group (t - 1) % 3 to find gBest of the
-// previous generation, and its workgroup 0 clears group (t + 1) % 3.
+// previous generation, and its workgroup 0 clears group (t + 1) % 3.  A swarm
+// with few workgroups uses only the first nsub sub-slots of each group.
 constexpr uint32_t kSubSlots = 64;
 constexpr uint32_t kSubStride = 32;
 constexpr uint32_t kGroups = 3;
 constexpr uint32_t kSubWords = kGroups * kSubSlots * kSubStride;  // 64-bit words
 
 struct SwarmDev {
-    float *rows;                 // [2][n][dp]
+    float *rows;                 // [2][n][stride] (floats, or packed 24-bit indices)
     float *fp;                   // [n] pBest fitness (FP32)
     uint32_t *st;                // [n] state word
     const float *s;              // [dp] shift, zero padded
@@ -47,13 +56,17 @@ struct SwarmDev {
     unsigned long long *keys;    // [trace_cap] gBest key per finished generation (ring)
     uint32_t *cnt;               // [trace_cap] improved pBests per finished generation (ring)
     unsigned long long *sub;     // [kGroups][kSubSlots][kSubStride]: key, then count
-    uint64_t buf;                // floats from row buffer 0 to row buffer 1 (n * dp)
-    uint32_t n, d, dp, chunks;   // chunks = ceil(d / 4)
+    uint64_t buf;                // 32-bit words from row buffer 0 to row buffer 1 (n * stride)
+    uint32_t n, d, dp, chunks;   // dp = d rounded up to 32; chunks = ceil(d / 4)
+    uint32_t stride;             // 32-bit words per row: dp (F32) or 3 chunks rounded up to 32 (U24)
+    int32_t storage;             // STORE_F32 or STORE_U24
     uint32_t trace_cap;
     uint32_t th0, th1, th2, r;   // integer thresholds and fresh-draw rescale
     float lo, span, span24;      // span24 = span * 2^-24 (exact)
     uint32_t key0, key1, swarm;  // Philox key and fourth counter word
     int32_t kind, order;
+    uint32_t nsub;               // sub-slots in use (a power of two <= kSubSlots)
+    uint32_t lanes;              // lanes per particle (batched kernel; a power of two)
 };
 
 // Launchers (each returns hipSuccess or the launch error).
