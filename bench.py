@@ -34,31 +34,36 @@ HBM_PEAK_GBS = 8000.0
 FP32_MATRIX_PEAK_TFLOPS = 157.3
 BYTES_PER_UPDATE = 12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = ("sso_device.hpp", "sso_layout.hpp", "gen_stream.hip", "gen_dense.hip",
-                  "resident.hip")
+# Sources each workload's generation kernel is compiled from: a committed
+# counter record is valid only while their hash is unchanged.
+KERNEL_SOURCES = {
+    "sphere": ("sso_device.hpp", "sso_layout.hpp", "resident.hip"),
+    "ripple": ("sso_device.hpp", "sso_layout.hpp", "gen_stream.hip"),
+    "dense": ("sso_device.hpp", "sso_layout.hpp", "gen_dense.hip"),
+}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_hash():
+def kernel_hash(kind):
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[kind]:
         with open(os.path.join(ROOT, "paper_2110_01470_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, per_launch_units):
+def measured_traffic(wl):
     """HBM bytes per launch from the committed counter summary, or None if the
-    kernels changed since the counters were taken."""
+    kernel changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            rec = json.load(fh).get(workload)
+            rec = json.load(fh).get(wl.name)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("kernel_hash") != kernel_hash():
+    if not rec or rec.get("kernel_hash") != kernel_hash(wl.kind):
         return None
     return rec.get("bytes_per_launch")
 
@@ -160,12 +165,12 @@ def main():
         achieved = flop / (ms_per_step / 1e3) / 1e12
         roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MATRIX_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": achieved / FP32_MATRIX_PEAK_TFLOPS,
-                    "traffic": measured_traffic(wl.name, 1)}
+                    "traffic": measured_traffic(wl)}
     else:
         byt = BYTES_PER_UPDATE * wl.n * wl.d
         achieved = byt / (ms_per_step / 1e3) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl.name, 1)}
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl)}
 
     cpu_gens = args.cpu_gens
     if cpu_gens is None:

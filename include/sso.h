@@ -161,6 +161,76 @@ const char *sso_strerror(int code);
  * sso_init/sso_workspace_bytes when ctx is NULL.  Empty string if none. */
 const char *sso_last_error(const sso_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Batched swarms.  `count` independent swarms advance together, one fused
+ * launch per generation for all of them, replayed from a HIP graph in
+ * blocks of 50 generations.  Each swarm is described by its own sso_config
+ * (size, box, thresholds, Philox key and swarm word, objective instance) and
+ * evolves exactly as the one-swarm library would evolve it with the same
+ * config and the same lanes per particle: the swarms share nothing but the
+ * launches.  Every swarm of a batch must have the same separable kind
+ * (SPHERE or RIPPLE), the same order and the same resolved storage; engine
+ * must be AUTO or STREAM; d <= 1024.  The lanes per particle of each swarm
+ * come from a mapping rule (a target number of 4-variable chunks per lane,
+ * "cpl") unless its config fixes `lanes`; sso_batch_tune() picks the rule by
+ * timing.  Ownership, synchronisation and return codes are as for the
+ * one-swarm calls; all swarms share the generation count.
+ * ------------------------------------------------------------------------ */
+typedef struct sso_batch sso_batch;
+
+/* Bytes of device workspace for the batch; 0 if any config is invalid or
+ * the batch constraints above do not hold (detail: sso_batch_last_error(NULL)). */
+size_t sso_batch_workspace_bytes(const sso_config *cfgs, uint32_t count);
+
+/* Validates, lays out, uploads every swarm's s (and w) synchronously, and
+ * enqueues the initialisation of every swarm (as sso_init does for one). */
+int sso_batch_init(const sso_config *cfgs, uint32_t count, void *dev_workspace,
+                   size_t workspace_bytes, void *hip_stream, sso_batch **out);
+
+/* Enqueue `generations` generations of every swarm. */
+int sso_batch_run(sso_batch *b, uint32_t generations);
+
+/* Autotuner.  Only right after sso_batch_init (no generations run yet):
+ * for each candidate rule cpl in {1, 2, 4, 8, 16} re-initialises the batch
+ * and times `generations` generations with HIP events; keeps the fastest
+ * rule and re-initialises under it, so the batch is again at generation 0.
+ * *cpl_out (may be NULL) receives the rule, ms_out[5] (may be NULL) the
+ * measured milliseconds per candidate.  Synchronises. */
+int sso_batch_tune(sso_batch *b, uint32_t generations, uint32_t *cpl_out, float *ms_out);
+
+/* The current mapping: *cpl_out the rule, lanes_out[count] each swarm's
+ * lanes per particle, *tiles_out the workgroups per generation launch.
+ * Any pointer may be NULL. */
+int sso_batch_mapping(sso_batch *b, uint32_t *cpl_out, uint32_t *lanes_out, uint32_t *tiles_out);
+
+/* Synchronise, then for every swarm k: f_out[k] its gBest fitness (FP32),
+ * idx_out[k] the gBest particle index, improved_out[k] the pBests replaced in
+ * the last generation; *gen_out the generations done.  Any pointer may be NULL. */
+int sso_batch_get_results(sso_batch *b, float *f_out, uint32_t *idx_out, uint32_t *improved_out,
+                          uint64_t *gen_out);
+
+/* Swarm k's gBest (as sso_get_best; g_out host [d_k]). */
+int sso_batch_get_best(sso_batch *b, uint32_t k, float *g_out, float *f_out, uint32_t *idx_out);
+
+/* Swarm k's state (as sso_get_state; x, p host [n_k * d_k], fp [n_k]). */
+int sso_batch_get_state(sso_batch *b, uint32_t k, float *x, float *p, float *fp, uint64_t *t);
+
+/* Replace swarm k's state (as sso_set_state).  t must equal the batch's
+ * generation count, else SSO_E_STATE. */
+int sso_batch_set_state(sso_batch *b, uint32_t k, const float *x, const float *p,
+                        const float *fp, uint64_t t);
+
+/* Swarm k's trace (as sso_get_trace). */
+int sso_batch_get_trace(sso_batch *b, uint32_t k, uint64_t first, uint32_t count, float *fg,
+                        uint32_t *gidx, uint32_t *improved);
+
+/* Free the batch (not the workspace).  NULL is allowed. */
+void sso_batch_destroy(sso_batch *b);
+
+/* Detail of the last error on b, or of the calling thread's last failed
+ * sso_batch_init/sso_batch_workspace_bytes when b is NULL. */
+const char *sso_batch_last_error(const sso_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

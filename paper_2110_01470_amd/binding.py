@@ -77,6 +77,18 @@ def load():
         "sso_destroy": (None, [P]),
         "sso_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sso_last_error": (ctypes.c_char_p, [P]),
+        "sso_batch_workspace_bytes": (ctypes.c_size_t, [cfgp, u32]),
+        "sso_batch_init": (ctypes.c_int, [cfgp, u32, P, ctypes.c_size_t, P, ctypes.POINTER(P)]),
+        "sso_batch_run": (ctypes.c_int, [P, u32]),
+        "sso_batch_tune": (ctypes.c_int, [P, u32, P, P]),
+        "sso_batch_mapping": (ctypes.c_int, [P, P, P, P]),
+        "sso_batch_get_results": (ctypes.c_int, [P, P, P, P, P]),
+        "sso_batch_get_best": (ctypes.c_int, [P, u32, P, P, P]),
+        "sso_batch_get_state": (ctypes.c_int, [P, u32, P, P, P, P]),
+        "sso_batch_set_state": (ctypes.c_int, [P, u32, P, P, P, u64]),
+        "sso_batch_get_trace": (ctypes.c_int, [P, u32, u64, u32, P, P, P]),
+        "sso_batch_destroy": (None, [P]),
+        "sso_batch_last_error": (ctypes.c_char_p, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -207,3 +219,144 @@ class Swarm:
         self._check(self._lib.sso_debug_rng(self._ctx, t, ctypes.c_void_p(out.data_ptr())))
         self.stream.synchronize()
         return out.cpu().numpy().view(np.uint32).reshape(self.n, self.d)
+
+
+# Candidate mapping rules of sso_batch_tune (target chunks per lane).
+TUNE_CANDIDATES = (1, 2, 4, 8, 16)
+
+
+class Batch:
+    """Many independent swarms advanced together (sso_batch_*).
+
+    `swarms` is a list of dicts with the keyword arguments of make_config
+    (n, d, kind, lo, hi, cg, cp, cw, seed, s, w, swarm_id, order, lanes,
+    trace_cap, storage)."""
+
+    def __init__(self, swarms, device="cuda", stream=None):
+        import torch
+
+        self._lib = load()
+        self.count = len(swarms)
+        self.sizes = [(int(sw["n"]), int(sw["d"])) for sw in swarms]
+        arr = (Config * self.count)()
+        self._keep = []
+        for k, sw in enumerate(swarms):
+            kw = dict(sw)
+            cfg, keep = make_config(kw.pop("n"), kw.pop("d"), kw.pop("kind"), kw.pop("lo"),
+                                    kw.pop("hi"), kw.pop("cg"), kw.pop("cp"), kw.pop("cw"),
+                                    kw.pop("seed"), kw.pop("s"), kw.pop("w", None), None, **kw)
+            arr[k] = cfg
+            self._keep.append(keep)
+        self._cfgs = arr
+        nbytes = self._lib.sso_batch_workspace_bytes(arr, self.count)
+        if nbytes == 0:
+            raise SSOError(E_INVAL, self._lib.sso_batch_last_error(None).decode())
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self._lib.sso_batch_init(arr, self.count, self.workspace.data_ptr(), nbytes,
+                                          ctypes.c_void_p(self.stream.cuda_stream),
+                                          ctypes.byref(ctx))
+        if rc != OK:
+            raise SSOError(rc, self._lib.sso_batch_last_error(None).decode())
+        self._ctx = ctx
+
+    def _check(self, rc):
+        if rc != OK:
+            raise SSOError(rc, self._lib.sso_batch_last_error(self._ctx).decode())
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.sso_batch_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, generations):
+        self._check(self._lib.sso_batch_run(self._ctx, generations))
+        return self
+
+    def step(self):
+        return self.run(1)
+
+    def tune(self, generations):
+        """(chosen rule, {rule: milliseconds})."""
+        cpl = ctypes.c_uint32()
+        ms = np.zeros(len(TUNE_CANDIDATES), np.float32)
+        self._check(self._lib.sso_batch_tune(self._ctx, generations, ctypes.byref(cpl), _ptr(ms)))
+        return int(cpl.value), dict(zip(TUNE_CANDIDATES, ms.tolist()))
+
+    def mapping(self):
+        """(rule, lanes per particle of every swarm, workgroups per launch)."""
+        cpl = ctypes.c_uint32()
+        tiles = ctypes.c_uint32()
+        lanes = np.zeros(self.count, np.uint32)
+        self._check(self._lib.sso_batch_mapping(self._ctx, ctypes.byref(cpl), _ptr(lanes),
+                                                ctypes.byref(tiles)))
+        return int(cpl.value), lanes, int(tiles.value)
+
+    def results(self):
+        """(fG [count], gidx [count], improved [count], generations done)."""
+        f = np.zeros(self.count, np.float32)
+        gi = np.zeros(self.count, np.uint32)
+        im = np.zeros(self.count, np.uint32)
+        gen = ctypes.c_uint64()
+        self._check(self._lib.sso_batch_get_results(self._ctx, _ptr(f), _ptr(gi), _ptr(im),
+                                                    ctypes.byref(gen)))
+        return f, gi, im, int(gen.value)
+
+    def view(self, k):
+        """Swarm k with the one-swarm read/write interface (no stepping)."""
+        return _BatchSwarm(self, k)
+
+
+class _BatchSwarm:
+    def __init__(self, batch, k):
+        self.batch, self.k = batch, k
+        # An index out of range reaches the library, which rejects it.
+        self.n, self.d = batch.sizes[k] if 0 <= k < batch.count else (1, 1)
+
+    def _check(self, rc):
+        self.batch._check(rc)
+
+    def best(self):
+        lib, ctx = self.batch._lib, self.batch._ctx
+        g = np.zeros(self.d, np.float32)
+        f = ctypes.c_float()
+        idx = ctypes.c_uint32()
+        self._check(lib.sso_batch_get_best(ctx, self.k, _ptr(g), ctypes.byref(f), ctypes.byref(idx)))
+        _, _, _, gen = self.state(with_rows=False)
+        return g, float(f.value), int(idx.value), gen
+
+    def state(self, with_rows=True):
+        lib, ctx = self.batch._lib, self.batch._ctx
+        x = np.zeros((self.n, self.d), np.float32) if with_rows else None
+        p = np.zeros((self.n, self.d), np.float32) if with_rows else None
+        fp = np.zeros(self.n, np.float32)
+        t = ctypes.c_uint64()
+        self._check(lib.sso_batch_get_state(ctx, self.k, _ptr(x), _ptr(p), _ptr(fp),
+                                            ctypes.byref(t)))
+        return x, p, fp, int(t.value)
+
+    def set_state(self, x, p, fp, t):
+        lib, ctx = self.batch._lib, self.batch._ctx
+        x = _f32(x).reshape(self.n, self.d)
+        p = _f32(p).reshape(self.n, self.d)
+        fp = _f32(fp).reshape(self.n)
+        self._check(lib.sso_batch_set_state(ctx, self.k, _ptr(x), _ptr(p), _ptr(fp), t))
+        return self
+
+    def trace(self, first, count):
+        lib, ctx = self.batch._lib, self.batch._ctx
+        fg = np.zeros(count, np.float32)
+        gi = np.zeros(count, np.uint32)
+        im = np.zeros(count, np.uint32)
+        self._check(lib.sso_batch_get_trace(ctx, self.k, first, count, _ptr(fg), _ptr(gi),
+                                            _ptr(im)))
+        return fg, gi, im

@@ -1,195 +1,13 @@
 // STREAM engine: one fused kernel per generation for the separable
-// objectives (sphere, ripple).
-//
-// One generation of Algorithm 2 in a single pass over the state: each group
-// of L lanes owns one particle and walks its row in float4 chunks
-// (chunk c, c + L, ...), so a wave's loads cover L * 16 contiguous bytes per
-// row -- whole 128-byte lines for L >= 8.  Per chunk a lane draws one Philox
-// block (four words, one per variable, Sec. 3.1), picks the four new values
-// by Eq. (2.1), writes them, and accumulates the objective terms.  The L
-// partial sums meet in a butterfly; every lane of the group then holds the
-// same fitness, takes the pBest decision of Algorithm 3 (strict <), and the
-// workgroup folds its (fitness, index) keys into the generation's gBest slot
-// with one atomicMin (Algorithm 4).  Generation t reads gBest from slot t-1
-// and clears slot t+1 for the next generation.
-//
-// With t == 0 the same kernel is the initialisation (kernel (I),
-// Sec. 2.3.1): X^0 is drawn uniformly from the generation-0 words, written
-// as the pBest row, and scored.
-#include "sso_device.hpp"
+// objectives (sphere, ripple) of one swarm; the body is in stream_body.hpp.
+#include "stream_body.hpp"
 
 namespace sso {
-
-// Measured on MI355X (ripple, N=65536, D=1000): one chunk of loads in flight
-// per lane, with occupancy hiding the latency, beats deeper unrolling (the
-// extra registers cost more waves than the extra loads gain).
-#ifndef SSO_STREAM_INFLIGHT
-#define SSO_STREAM_INFLIGHT 1
-#endif
-#ifndef SSO_STREAM_WAVES
-#define SSO_STREAM_WAVES 4
-#endif
-constexpr int kWaves = SSO_STREAM_WAVES;
-constexpr int kInFlight = SSO_STREAM_INFLIGHT;  // chunks whose loads a lane issues before computing
-
-// Words a chunk of 4 variables takes in a row.
-template <class Store>
-constexpr uint32_t chunk_words() { return sizeof(typename Store::T) == 16 && !Store::kPacked ? 4u : 3u; }
-
-// One generation t (the initialisation when INIT) for the particles of
-// workgroup blk of swarm S, with L lanes per particle: the compile-time LT,
-// or the power of two l when LT == 0 (the batched kernel, whose workgroups
-// belong to swarms of different widths).
-// RAGGED: d is not a multiple of 4, so the last chunk has padding columns.
-// STAGE: the shift, the ripple weights and the gBest row are copied into LDS
-// once per workgroup (dynamic LDS, see stage_bytes) and read from there, so
-// the vector-memory path carries only the particle's own pBest and position.
-template <int KIND, int LT, bool EQ21, bool INIT, bool RAGGED, bool STAGE, class Store>
-__device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint32_t blk,
-                                            uint32_t l)
-{
-    using T = typename Store::T;
-    extern __shared__ f4 lds_dyn[];
-    constexpr uint32_t CW = chunk_words<Store>();
-    const uint32_t L = LT ? (uint32_t)LT : l;
-    const uint32_t lsh = LT ? (uint32_t)__builtin_ctz((uint32_t)LT) : (uint32_t)__builtin_ctz(l);
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63u, wave = tid >> 6;
-    const uint32_t ln = lane & (L - 1u);
-    // 64 / L particles per wave.
-    const uint32_t i = ((blk * kWaves + wave) << (6u - lsh)) + (lane >> lsh);
-    const bool valid = i < S.n;
-
-    uint32_t prow = 0;
-    bool alias = true;
-    float fpi = 0.0f;
-    if (!INIT && valid) {
-        const uint32_t st = S.st[i];
-        fpi = S.fp[i];
-        prow = st & ST_ROW;
-        alias = (st & ST_ALIAS) != 0u;
-    }
-    uint32_t *rows = reinterpret_cast<uint32_t *>(S.rows);
-    const size_t ioff = (size_t)(valid ? i : 0u) * S.stride;
-    const uint32_t *prow_ptr = rows + prow * S.buf + ioff;
-    // INIT writes the pBest row (row 0); a generation writes the other row.
-    uint32_t *xrow_ptr = rows + (INIT ? 0u : (1u - prow)) * S.buf + ioff;
-    // The position is read from the pBest row itself when aliased.
-    const uint32_t *xsrc = alias ? prow_ptr : xrow_ptr;
-    const f4 *s4 = reinterpret_cast<const f4 *>(S.s);
-    const f4 *w4 = reinterpret_cast<const f4 *>(S.w);
-    const f4 zero = f4{0.f, 0.f, 0.f, 0.f};
-    f4 *ls = lds_dyn;                                              // [chunks] shift
-    f4 *lw = lds_dyn + S.chunks;                                   // [chunks] weights
-    uint32_t *lg = reinterpret_cast<uint32_t *>(lds_dyn + (KIND == OBJ_RIPPLE ? 2 : 1) * S.chunks);
-
-    // Loads that do not depend on gBest go out before the start-of-generation
-    // barrier: the shift and weights for staging, this lane's first pBest and
-    // position.
-    if constexpr (STAGE) {
-        for (uint32_t q = tid; q < S.chunks; q += blockDim.x) {
-            ls[q] = s4[q];
-            if (KIND == OBJ_RIPPLE) lw[q] = w4[q];
-        }
-    }
-    T pv[kInFlight], xv[kInFlight], gv[kInFlight];
-    if (!INIT && valid) {
-#pragma unroll
-        for (int u = 0; u < kInFlight; ++u) {
-            const uint32_t c = ln + u * L;
-            if (c < S.chunks) {
-                pv[u] = Store::load(prow_ptr, c);
-                xv[u] = Store::load(xsrc, c);
-            }
-        }
-    }
-    // gBest of the previous generation (unused at t == 0).
-    const uint32_t *grow_ptr = nullptr;
-    if constexpr (!INIT) {
-        const uint32_t glow = (uint32_t)generation_begin(S, t, blk);
-        const uint32_t gidx = min(glow >> 1, S.n - 1u);
-        grow_ptr = rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.stride;
-        if constexpr (STAGE) {
-            for (uint32_t q = tid; q < S.chunks * CW; q += blockDim.x) lg[q] = grow_ptr[q];
-        }
-    }
-    if constexpr (STAGE) __syncthreads();
-
-    float acc = 0.0f;
-    if (valid) {
-        for (uint32_t c0 = ln; c0 < S.chunks; c0 += kInFlight * L) {
-            if constexpr (!INIT) {
-#pragma unroll
-                for (int u = 0; u < kInFlight; ++u) {
-                    const uint32_t c = c0 + u * L;
-                    if (c < S.chunks) {
-                        if (c0 != ln) {  // later batches: rows not issued yet
-                            pv[u] = Store::load(prow_ptr, c);
-                            xv[u] = Store::load(xsrc, c);
-                        }
-                        gv[u] = STAGE ? Store::load(lg, c) : Store::load(grow_ptr, c);
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kInFlight; ++u) {
-                const uint32_t c = c0 + u * L;
-                if (c < S.chunks) {
-                    const uint4 k = words4(S, c, i, t);
-                    T xn;
-                    if constexpr (INIT)
-                        xn = Store::init(S, k);
-                    else
-                        xn = Store::template select<EQ21>(S, k, gv[u], pv[u], xv[u]);
-                    Store::store(xrow_ptr, c, xn);
-                    const f4 sv = STAGE ? ls[c] : s4[c];
-                    const f4 wv = (KIND == OBJ_RIPPLE) ? (STAGE ? lw[c] : w4[c]) : zero;
-                    const f4 xf = Store::value(S, xn);
-                    if constexpr (RAGGED)
-                        acc += terms4<KIND>(xf, sv, wv, 4u * c, S.d);
-                    else
-                        acc += terms4_full<KIND>(xf, sv, wv);
-                }
-            }
-        }
-    }
-    // Butterfly over the L lanes of the particle (the masks are immediates;
-    // with a runtime width the steps above it are skipped uniformly).
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1)
-        if ((uint32_t)m < L) acc += __shfl_xor(acc, m, 64);
-
-    // Algorithm 3: replace the pBest on a strict improvement (NaN never does).
-    const bool improved = valid && (INIT || acc < fpi);
-    uint32_t row = prow;
-    float fnew = fpi;
-    if (improved) {
-        row = INIT ? 0u : 1u - prow;
-        fnew = acc;
-    }
-    if (valid && ln == 0) {
-        S.st[i] = improved ? (row | ST_ALIAS) : row;
-        if (improved) S.fp[i] = fnew;
-    }
-    const unsigned long long key = valid ? gbest_key(fnew, i, row) : ~0ull;
-
-    generation_commit<kWaves>(S, t, blk, key, (improved && ln == 0) ? 1u : 0u);
-}
 
 template <int KIND, int L, bool EQ21, bool INIT, bool RAGGED, bool STAGE, class Store>
 __global__ __launch_bounds__(64 * kWaves) void k_stream(SwarmDev S, uint32_t t)
 {
     stream_body<KIND, L, EQ21, INIT, RAGGED, STAGE, Store>(S, t, blockIdx.x, (uint32_t)L);
-}
-
-// Dynamic LDS of the staged kernels: shift, ripple weights, gBest row.
-constexpr uint32_t kStageMaxChunks = 256;  // d <= 1024
-
-template <int KIND, class Store>
-static size_t stage_bytes(const SwarmDev &S)
-{
-    return (size_t)S.chunks * 16u * (KIND == OBJ_RIPPLE ? 2u : 1u) +
-           (size_t)S.chunks * chunk_words<Store>() * 4u;
 }
 
 template <int KIND, int L, bool EQ21, bool RAGGED, bool STAGE, class Store>

@@ -1,0 +1,54 @@
+// Host helpers shared by the one-swarm API (sso_api.hip) and the batch API
+// (sso_batch.hip): configuration checks, per-swarm parameters, uploads, and
+// the state import/export of one swarm held in device memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "sso.h"
+#include "sso_layout.hpp"
+
+namespace sso {
+namespace host {
+
+constexpr uint32_t kDefaultTraceCap = 4096;
+
+size_t align256(size_t x);
+uint32_t round_up(uint32_t x, uint32_t m);
+// ceil(c 2^32) for c in [0, 1] (exact: the product by 2^32 is exact).
+uint64_t threshold(double c);
+// SSO_OK or an error code with the reason in *why.
+int validate(const sso_config *c, std::string *why);
+// Engine and row storage a valid configuration resolves to.
+void resolve(const sso_config &c, int *engine, int *storage);
+int hip_fail(std::string *err, hipError_t e, const char *what);
+
+// Integer thresholds of Eq. (2.1) in the configured order, the fresh-draw
+// rescale, the box, the Philox key and swarm word, the kind and the order.
+void set_params(const sso_config &c, SwarmDev &S);
+// Copies s (and w for RIPPLE) zero-padded to S.dp floats; synchronous.
+int upload_separable(const sso_config &c, const SwarmDev &S, hipStream_t st, std::string *err);
+
+uint32_t orderable_host(float f);
+float from_orderable(uint32_t o);
+
+// The operations below act on one swarm whose generation count is t; the
+// ones that read the device synchronise `st` first.
+int current_result(const SwarmDev &S, uint64_t t, std::string *err, unsigned long long *key,
+                   uint32_t *count);
+int get_best(const SwarmDev &S, hipStream_t st, uint64_t t, std::string *err, float *g_out,
+             float *f_out, uint32_t *idx_out);
+int get_state(const SwarmDev &S, hipStream_t st, std::string *err, float *x, float *p, float *fp);
+// Imports a state with generation count t: pBests into row 0, gBest = the
+// lowest-index argmin of fp, trace ring restarted at t.
+int set_state(const SwarmDev &S, hipStream_t st, uint64_t t, std::string *err, const float *x,
+              const float *p, const float *fp);
+int get_trace(const SwarmDev &S, hipStream_t st, uint64_t t_now, uint64_t trace_base,
+              std::string *err, uint64_t first, uint32_t count, float *fg, uint32_t *gidx,
+              uint32_t *improved);
+
+}  // namespace host
+}  // namespace sso

@@ -69,6 +69,22 @@ struct SwarmDev {
     uint32_t lanes;              // lanes per particle (batched kernel; a power of two)
 };
 
+// Batched engine: many independent separable swarms advance together, one
+// launch per generation.  Workgroup b of a launch runs block tiles[2b+1] of
+// swarm tiles[2b], whose parameters are table[tiles[2b]]; all swarms share
+// the objective kind, the interval order and the row storage.  Generation
+// launches read t = *tbase + j, so a captured block of launches (j = 1..K
+// followed by a node that adds K to *tbase) can be replayed unchanged.
+struct BatchDev {
+    const SwarmDev *table;       // [count]
+    const uint32_t *tiles;       // [ntiles][2]: swarm, block within the swarm
+    uint32_t *tbase;             // generations completed before the current block
+    unsigned long long *results; // [count][2]: gBest key, improved count (collect)
+    uint32_t count, ntiles;
+    uint32_t lds;                // dynamic LDS bytes per workgroup (largest swarm)
+    int32_t kind, order, storage;
+};
+
 // Launchers (each returns hipSuccess or the launch error).
 int launch_stream_generation(const SwarmDev &S, uint32_t t, uint32_t lanes, void *stream);
 int launch_dense_generation(const SwarmDev &S, uint32_t t, void *stream);
@@ -77,6 +93,17 @@ int launch_debug_rng(const SwarmDev &S, uint32_t t, uint32_t *out, void *stream)
 int launch_resident(const SwarmDev &S, uint32_t t_first, uint32_t generations, void *stream);
 bool resident_fits(uint32_t n, uint32_t d, int kind);
 uint64_t dense_matrix_floats(uint32_t d);
+
+int launch_batch_fill(const BatchDev &B, void *stream);    // every swarm's trace ring and sub-slots
+int launch_batch_init(const BatchDev &B, void *stream);    // generation 0 of every swarm
+int launch_batch_set_base(const BatchDev &B, uint32_t t, void *stream);
+// Generations *tbase + 1 .. *tbase + k, then *tbase += k.
+int launch_batch_generations(const BatchDev &B, uint32_t k, void *stream);
+// The same k launches and the base update as nodes of a new graph.
+int batch_graph(const BatchDev &B, uint32_t k, void **graph_out);
+// results[s] = gBest key and improved count of generation t, for every swarm.
+int launch_batch_collect(const BatchDev &B, uint32_t t, void *stream);
+size_t batch_stage_bytes(int kind, int storage, uint32_t chunks);
 void dense_pack_matrix(const float *a, uint32_t d, float *out);
 
 }  // namespace sso

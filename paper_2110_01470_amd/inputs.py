@@ -57,6 +57,58 @@ WORKLOADS = {
 }
 
 
+@dataclasses.dataclass(frozen=True)
+class BatchWorkload:
+    """Many independent swarms of uneven size, each with its own objective.
+
+    Swarm k draws its size, dimension and thresholds from PCG64 seeded with
+    the sequence (seed + k, 0): n ~ U{n_lo..n_hi}, d ~ U{d_lo..d_hi},
+    cg ~ U[cg], cp ~ U[cp], cw ~ U[cw] (disjoint ranges, so cg < cp < cw);
+    its objective instance comes from make_objective with seed + k, and its
+    Philox key is seed + k with swarm word k."""
+
+    name: str
+    kind: str
+    count: int
+    n_range: tuple
+    d_range: tuple
+    lo: float
+    hi: float
+    cg_range: tuple
+    cp_range: tuple
+    cw_range: tuple
+    generations: int
+    seed: int
+    s_lo: float
+    s_hi: float
+
+    def swarm(self, k: int) -> dict:
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([self.seed + k, 0])))
+        n = int(rng.integers(self.n_range[0], self.n_range[1] + 1))
+        d = int(rng.integers(self.d_range[0], self.d_range[1] + 1))
+        cg = float(rng.uniform(*self.cg_range))
+        cp = float(rng.uniform(*self.cp_range))
+        cw = float(rng.uniform(*self.cw_range))
+        s, w, _ = make_objective(self.kind, d, self.seed + k, self.s_lo, self.s_hi)
+        return dict(n=n, d=d, kind=self.kind, lo=self.lo, hi=self.hi, cg=cg, cp=cp, cw=cw,
+                    seed=self.seed + k, swarm_id=k, s=s, w=w)
+
+    def swarms(self) -> list:
+        return [self.swarm(k) for k in range(self.count)]
+
+    def scaled(self, **changes) -> "BatchWorkload":
+        return dataclasses.replace(self, **changes)
+
+
+BATCH_WORKLOADS = {
+    b.name: b
+    for b in (
+        BatchWorkload("batch512_ripple", "ripple", 512, (32, 4096), (10, 500), -100.0, 100.0,
+                      (0.3, 0.5), (0.6, 0.75), (0.85, 0.95), 2000, 4_000_000, -50.0, 50.0),
+    )
+}
+
+
 def make_objective(kind: str, d: int, seed: int, s_lo: float, s_hi: float):
     """(s, w, a) as FP32 arrays; w is None unless ripple, a is None unless dense."""
     if kind not in KINDS:

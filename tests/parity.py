@@ -32,16 +32,22 @@ class Pair:
 
     def __init__(self, kind, n, d, lo=-100.0, hi=100.0, cg=0.4, cp=0.7, cw=0.9, seed=1,
                  s_range=(-50.0, 50.0), order=oracle.ORDER_GPS, engine="auto", lanes=0,
-                 swarm_id=0, trace_cap=0, storage="auto"):
+                 swarm_id=0, trace_cap=0, storage="auto", objective=None, gpu=None):
+        """`objective` = (s, w, a) overrides the seeded instance; `gpu` is an
+        already built GPU side (a swarm of a batch) instead of a new Swarm."""
         from paper_2110_01470_amd.binding import Swarm
 
         self.kind, self.n, self.d = kind, n, d
-        self.s, self.w, self.a = make_objective(kind, d, seed, *s_range)
+        if objective is None:
+            objective = make_objective(kind, d, seed, *s_range)
+        self.s, self.w, self.a = objective
         self.orc = oracle.Swarm(n, d, KIND[kind], lo, hi, cg, cp, cw, seed, self.s, self.w,
                                 self.a, swarm=swarm_id, order=order)
-        self.gpu = Swarm(n, d, kind, lo, hi, cg, cp, cw, seed, self.s, self.w, self.a,
-                         swarm_id=swarm_id, order=order, engine=engine, lanes=lanes,
-                         trace_cap=trace_cap, storage=storage)
+        if gpu is None:
+            gpu = Swarm(n, d, kind, lo, hi, cg, cp, cw, seed, self.s, self.w, self.a,
+                        swarm_id=swarm_id, order=order, engine=engine, lanes=lanes,
+                        trace_cap=trace_cap, storage=storage)
+        self.gpu = gpu
         self.orc.init()
         self.band_events = 0
         self.prev_fp64 = self.orc.fp64.copy()
@@ -100,3 +106,45 @@ def _first_diff(a, b, name):
         return f"{name} equal"
     i = tuple(idx[0])
     return f"{name} differs at {i}: {a[i]!r} vs {b[i]!r} ({len(idx)} elements differ)"
+
+
+def oracle_run_with_trace(orc, k):
+    """k oracle generations; per generation the gBest fitness (FP64), gBest
+    index, improved count, and whether any pBest decision was a near-tie."""
+    fg, gi, im, tie = [], [], [], []
+    for _ in range(k):
+        prev = orc.fp64.copy()
+        orc.step()
+        fg.append(orc.fp64[orc.gidx])
+        gi.append(orc.gidx)
+        im.append(int(orc.improved.sum()))
+        close = np.abs(orc.fx64 - prev) <= BAND * np.maximum(np.abs(orc.fx64), np.abs(prev))
+        srt = np.sort(orc.fp64)
+        gtie = srt.size > 1 and near(srt[0], srt[1])
+        tie.append(bool(close.any()) or bool(gtie))
+    return np.array(fg), np.array(gi, np.uint32), np.array(im, np.uint32), np.array(tie)
+
+
+def compare_after_run(pair, first, trace):
+    """After the oracle ran len(trace[0]) generations with oracle_run_with_trace
+    and the GPU ran the same generations in one go: either the states agree
+    (then the GPU trace must match the oracle's), or the first generation
+    whose gBest index or improved count differs must be one in which the
+    oracle saw a near-tie decision.  Returns the number of such divergences
+    (0 or 1); a diverged swarm is re-synchronised to the oracle."""
+    fgs, gis, ims, ties = trace
+    x, p, fp, t = pair.gpu.state()
+    fg, gi, im = pair.gpu.trace(first, len(gis))
+    if np.array_equal(x, pair.orc.x) and np.array_equal(p, pair.orc.p):
+        assert np.array_equal(gi, gis), "equal states but different gBest indices"
+        assert np.array_equal(im, ims), "equal states but different improvement counts"
+        assert np.all(np.abs(fg - fgs) <= REL_TOL * np.abs(fgs))
+        pair.prev_fp64 = pair.orc.fp64.copy()
+        pair.compare()
+        return 0
+    diff = np.where((gi != gis) | (im != ims))[0]
+    assert diff.size > 0, "states differ although every traced decision agrees"
+    k = int(diff[0])
+    assert ties[k], f"divergence at generation {first + k} without a near-tie in the oracle"
+    pair.gpu.set_state(pair.orc.x, pair.orc.p, pair.orc.fp, pair.orc.t)
+    return 1

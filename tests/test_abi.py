@@ -21,9 +21,10 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ("sso_init", "sso_step", "sso_run", "sso_get_best"):
+    for required in ("sso_init", "sso_step", "sso_run", "sso_get_best", "sso_batch_init",
+                     "sso_batch_run", "sso_batch_tune", "sso_batch_get_results"):
         assert required in names
-    assert len(names) == 12
+    assert len(names) == 24
 
 
 def test_library_exports_every_declared_symbol():
@@ -94,3 +95,64 @@ def test_init_rejects_bad_workspace_before_touching_a_device():
     assert lib.sso_init(ctypes.byref(c), ctypes.c_void_p(4096), nbytes - 1, None,
                         ctypes.byref(ctx)) == binding.E_NOMEM
     assert ctx.value is None
+
+
+def batch_cfgs(*changes):
+    """A batch of ripple swarms; changes[k] (a dict) alters swarm k."""
+    out = []
+    for k, ch in enumerate(changes):
+        d = ch.get("d", 20)
+        base = dict(n=50 + k, d=d, kind="ripple", lo=-10.0, hi=10.0, cg=0.4, cp=0.7, cw=0.9,
+                    seed=k, swarm_id=k, s=np.zeros(d, np.float32), w=np.ones(d, np.float32))
+        base.update(ch)
+        out.append(binding.make_config(**base))
+    arr = (binding.Config * len(out))(*[c for c, _ in out])
+    return arr, [keep for _, keep in out]
+
+
+def test_batch_workspace_bytes_adds_up_the_swarms():
+    lib = binding.load()
+    arr, keep = batch_cfgs({}, {"n": 1000, "d": 500}, {"d": 3})
+    nbytes = lib.sso_batch_workspace_bytes(arr, 3)
+    # 24-bit rows: 3 words per 4 variables, two rows per particle, packed.
+    rows = sum(2 * n * 3 * ((d + 3) // 4) * 4 for n, d in ((50, 20), (1000, 500), (52, 3)))
+    assert nbytes >= rows + 3 * 4096 * 12
+    arr, keep = batch_cfgs({"storage": "f32"}, {"n": 1000, "d": 500, "storage": "f32"},
+                           {"d": 3, "storage": "f32"})
+    f32 = lib.sso_batch_workspace_bytes(arr, 3)
+    assert f32 > nbytes
+    # A swarm small enough for the one-swarm resident engine still runs in a
+    # batch (on the STREAM body), 24-bit rows included.
+    arr, keep = batch_cfgs({"n": 1, "d": 1, "storage": "u24"})
+    assert lib.sso_batch_workspace_bytes(arr, 1) > 0
+
+
+@pytest.mark.parametrize("changes", [
+    ({}, {"kind": "sphere", "w": None}),        # mixed kinds
+    ({}, {"order": 1, "cg": 0.9, "cw": 0.4}),   # mixed orders
+    ({}, {"storage": "f32"}),                   # mixed storage
+    ({"kind": "dense", "d": 8, "a": np.eye(8, dtype=np.float32)},),
+    ({"engine": "resident"},),
+    ({"d": 1025},),
+    ({}, {"cg": 0.95}),                          # one invalid swarm
+])
+def test_invalid_batches_are_rejected(changes):
+    lib = binding.load()
+    arr, keep = batch_cfgs(*changes)
+    assert lib.sso_batch_workspace_bytes(arr, len(changes)) == 0
+    assert lib.sso_batch_last_error(None)
+
+
+def test_batch_init_rejects_bad_arguments_before_touching_a_device():
+    lib = binding.load()
+    arr, keep = batch_cfgs({}, {})
+    assert lib.sso_batch_workspace_bytes(arr, 0) == 0
+    assert lib.sso_batch_workspace_bytes(None, 2) == 0
+    nbytes = lib.sso_batch_workspace_bytes(arr, 2)
+    b = ctypes.c_void_p()
+    assert lib.sso_batch_init(arr, 2, ctypes.c_void_p(4096 + 8), nbytes, None,
+                              ctypes.byref(b)) == binding.E_INVAL
+    assert lib.sso_batch_init(arr, 2, ctypes.c_void_p(4096), nbytes - 1, None,
+                              ctypes.byref(b)) == binding.E_NOMEM
+    assert b.value is None
+    lib.sso_batch_destroy(None)
