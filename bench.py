@@ -38,8 +38,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # counter record is valid only while their hash is unchanged.
 KERNEL_SOURCES = {
     "sphere": ("sso_device.hpp", "sso_layout.hpp", "resident.hip"),
-    "ripple": ("sso_device.hpp", "sso_layout.hpp", "gen_stream.hip"),
+    "ripple": ("sso_device.hpp", "sso_layout.hpp", "stream_body.hpp", "gen_stream.hip"),
     "dense": ("sso_device.hpp", "sso_layout.hpp", "gen_dense.hip"),
+    "batch": ("sso_device.hpp", "sso_layout.hpp", "stream_body.hpp", "gen_batch.hip"),
 }
 
 
@@ -63,7 +64,8 @@ def measured_traffic(wl):
             rec = json.load(fh).get(wl.name)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("kernel_hash") != kernel_hash(wl.kind):
+    kind = "batch" if hasattr(wl, "count") else wl.kind
+    if not rec or rec.get("kernel_hash") != kernel_hash(kind):
         return None
     return rec.get("bytes_per_launch")
 
@@ -97,6 +99,46 @@ def time_gpu(wl, steps, warmup, engine):
     return ms, fg, gen
 
 
+def time_gpu_batch(swarms, steps, tune_gens):
+    import torch
+
+    from paper_2110_01470_amd.binding import Batch
+
+    stream = torch.cuda.Stream()
+    batch = Batch(swarms, stream=stream)
+    cpl, tune_ms = batch.tune(tune_gens)
+    log(f"mapping rule {cpl} chunks per lane; tuner ms per {tune_gens} generations: {tune_ms}")
+    stream.synchronize()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    batch.run(steps)
+    stop.record(stream)
+    stop.synchronize()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    f, gi, im, gen = batch.results()
+    return ms, float(f.min()), gen, cpl, batch.mapping()[2]
+
+
+def time_oracle_batch(swarms, gens):
+    import oracle
+
+    sec = 0.0
+    updates = 0
+    for sw in swarms:
+        kind = {"sphere": oracle.SPHERE, "ripple": oracle.RIPPLE}[sw["kind"]]
+        orc = oracle.Swarm(sw["n"], sw["d"], kind, sw["lo"], sw["hi"], sw["cg"], sw["cp"], sw["cw"],
+                           sw["seed"], sw["s"], sw["w"], None, swarm=sw["swarm_id"])
+        orc.init()
+        t0 = time.perf_counter()
+        orc.run(gens)
+        sec += time.perf_counter() - t0
+        updates += sw["n"] * sw["d"] * gens
+    return updates, sec
+
+
 def time_oracle(wl, gens):
     import oracle
 
@@ -126,13 +168,16 @@ def copy_calibration(nbytes, reps=5):
 
 
 def main():
-    from paper_2110_01470_amd.inputs import WORKLOADS
+    from paper_2110_01470_amd.inputs import BATCH_WORKLOADS, WORKLOADS
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed generations (default: the workload's)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="ripple_n65536_d1000", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="ripple_n65536_d1000",
+                    choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS))
+    ap.add_argument("--tune-gens", type=int, default=5,
+                    help="generations the batch mapping tuner times per candidate")
     ap.add_argument("--engine", default="auto", choices=["auto", "stream", "resident"])
     ap.add_argument("--cpu-gens", type=int, default=None,
                     help="oracle generations for cpu_baseline (0 = skip)")
@@ -149,6 +194,10 @@ def main():
               "(the swarm of one GPU is the unit; see the sharding notes in DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload in BATCH_WORKLOADS:
+        bench_batch(BATCH_WORKLOADS[args.workload], args)
+        return
 
     wl = WORKLOADS[args.workload]
     steps = args.steps if args.steps is not None else wl.generations
@@ -202,6 +251,54 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "objective": wl.kind, "n": wl.n, "d": wl.d,
                    "generations": steps, "engine": args.engine},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def bench_batch(bw, args):
+    """The batched workload: every swarm advances `steps` generations; a step
+    is one generation of all swarms (one launch, replayed from graphs)."""
+    from paper_2110_01470_amd.binding import TUNE_CANDIDATES
+
+    steps = args.steps if args.steps is not None else bw.generations
+    swarms = bw.swarms()
+    total = sum(sw["n"] * sw["d"] for sw in swarms)
+    log(f"workload {bw.name}: {bw.count} swarms, {total} variables, steps={steps}")
+    ms, fbest, gen, cpl, tiles = time_gpu_batch(swarms, steps, args.tune_gens)
+    sec = ms / 1e3
+    ms_per_step = ms / steps
+    log(f"gpu: {ms:.3f} ms for {steps} generations, best fG over swarms={fbest:.6g} at t={gen}")
+    byt = BYTES_PER_UPDATE * total
+    achieved = byt / (ms_per_step / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(bw)}
+    cpu = None
+    if args.cpu_gens is None or args.cpu_gens > 0:
+        gens = args.cpu_gens or 1
+        updates, csec = time_oracle_batch(swarms, gens)
+        cpu = {"value": updates / csec, "unit": "particle-var updates/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{gens} generation(s) of each of the {bw.count} swarms of {bw.name} "
+                         f"after initialisation, single-threaded FP64 oracle, {csec:.2f} s"}
+        log(f"cpu oracle: {csec:.2f} s for {updates} updates")
+    rec = {
+        "metric": "particle-var updates/s incl. fitness",
+        "value": total * steps / sec,
+        "unit": "particle-var updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": len(TUNE_CANDIDATES) * args.tune_gens,  # the tuner's timed generations
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": bw.name, "objective": bw.kind, "swarms": bw.count,
+                   "variables": total, "generations": steps, "mapping_rule": cpl,
+                   "workgroups_per_launch": tiles, "graph_block": 50},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
