@@ -21,7 +21,7 @@ namespace {
 constexpr uint32_t kGraphBlock = 50;       // generations per replayed graph
 constexpr uint32_t kMaxSwarms = 1u << 20;
 constexpr uint32_t kBatchMaxD = 1024;      // LDS staging of s, w and gBest
-constexpr uint32_t kWavesPerBlock = 4;     // the batched kernel's workgroup (4 waves)
+constexpr uint32_t kWavesPerBlock = kStreamWaves;  // the batched kernel's workgroup
 constexpr uint32_t kSubPerSlot = 8;        // workgroups per gBest sub-slot, at most
 const uint32_t kCandidates[] = {1, 2, 4, 8, 16};
 constexpr uint32_t kDefaultCpl = 8;

@@ -104,10 +104,10 @@ struct U24x4 {
 struct StoreF32 {
     using T = f4;
     static constexpr bool kPacked = false;
-    __device__ static T load(const uint32_t *row, uint32_t c)
-    {
-        return reinterpret_cast<const f4 *>(row)[c];
-    }
+    using R = f4;
+    __device__ static R load_raw(const uint32_t *row, uint32_t c) { return reinterpret_cast<const f4 *>(row)[c]; }
+    __device__ static T unpack(R v) { return v; }
+    __device__ static T load(const uint32_t *row, uint32_t c) { return load_raw(row, c); }
     __device__ static void store(uint32_t *row, uint32_t c, T v) { reinterpret_cast<f4 *>(row)[c] = v; }
     __device__ static T init(const SwarmDev &S, uint4 k) { return init4(S, k); }
     template <bool EQ21>
@@ -134,12 +134,15 @@ __device__ __forceinline__ uint32_t select_u(const SwarmDev &S, uint32_t k, uint
 struct StoreU24 {
     using T = u4v;
     static constexpr bool kPacked = true;
-    __device__ static T load(const uint32_t *row, uint32_t c)
+    // R is the chunk as stored (loaded early, unpacked when used).
+    using R = U24x4;
+    __device__ static R load_raw(const uint32_t *row, uint32_t c) { return reinterpret_cast<const U24x4 *>(row)[c]; }
+    __device__ static T unpack(R q)
     {
-        const U24x4 q = reinterpret_cast<const U24x4 *>(row)[c];
         return T{q.w0 & 0xFFFFFFu, __builtin_amdgcn_alignbit(q.w1, q.w0, 24) & 0xFFFFFFu,
                  __builtin_amdgcn_alignbit(q.w2, q.w1, 16) & 0xFFFFFFu, q.w2 >> 8};
     }
+    __device__ static T load(const uint32_t *row, uint32_t c) { return unpack(load_raw(row, c)); }
     __device__ static void store(uint32_t *row, uint32_t c, T u)
     {
         reinterpret_cast<U24x4 *>(row)[c] =

@@ -31,6 +31,12 @@ enum { STORE_F32 = 0, STORE_U24 = 1 };
 enum : uint32_t { ST_ROW = 1u, ST_ALIAS = 2u };
 
 constexpr uint32_t kRowAlign = 32;      // floats per row alignment unit (128 B)
+// Waves per workgroup of the STREAM and batched kernels (measured on the
+// ripple workload: 4, 8 and 16 waves run within 0.5 % of each other).
+#ifndef SSO_STREAM_WAVES
+#define SSO_STREAM_WAVES 4
+#endif
+constexpr uint32_t kStreamWaves = SSO_STREAM_WAVES;
 constexpr uint32_t kDenseMaxD = 256;    // dense kernel limit on d
 
 // gBest hand-off between generations.  Every workgroup folds its (fitness,

@@ -20,17 +20,7 @@
 
 namespace sso {
 
-// Measured on MI355X (ripple, N=65536, D=1000): one chunk of loads in flight
-// per lane, with occupancy hiding the latency, beats deeper unrolling (the
-// extra registers cost more waves than the extra loads gain).
-#ifndef SSO_STREAM_INFLIGHT
-#define SSO_STREAM_INFLIGHT 1
-#endif
-#ifndef SSO_STREAM_WAVES
-#define SSO_STREAM_WAVES 4
-#endif
-constexpr int kWaves = SSO_STREAM_WAVES;
-constexpr int kInFlight = SSO_STREAM_INFLIGHT;  // chunks whose loads a lane issues before computing
+constexpr int kWaves = (int)kStreamWaves;
 
 // Words a chunk of 4 variables takes in a row.
 template <class Store>
@@ -95,23 +85,17 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
 
     // Loads that do not depend on gBest go out before the start-of-generation
     // barrier: the shift and weights for staging, this lane's first pBest and
-    // position.
+    // position (as stored; unpacked when the chunk is computed).
     if constexpr (STAGE) {
         for (uint32_t q = tid; q < S.chunks; q += blockDim.x) {
             ls[q] = s4[q];
             if (KIND == OBJ_RIPPLE) lw[q] = w4[q];
         }
     }
-    T pv[kInFlight], xv[kInFlight], gv[kInFlight];
-    if (!INIT && valid) {
-#pragma unroll
-        for (int u = 0; u < kInFlight; ++u) {
-            const uint32_t c = ln + u * L;
-            if (c < S.chunks) {
-                pv[u] = Store::load(prow_ptr, c);
-                xv[u] = Store::load(xsrc, c);
-            }
-        }
+    typename Store::R pr{}, xr{};
+    if (!INIT && valid && ln < S.chunks) {
+        pr = Store::load_raw(prow_ptr, ln);
+        xr = Store::load_raw(xsrc, ln);
     }
     // gBest of the previous generation (unused at t == 0).
     const uint32_t *grow_ptr = nullptr;
@@ -127,40 +111,33 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
 
     float acc = 0.0f;
     if (valid) {
-        for (uint32_t c0 = ln; c0 < S.chunks; c0 += kInFlight * L) {
-            if constexpr (!INIT) {
-#pragma unroll
-                for (int u = 0; u < kInFlight; ++u) {
-                    const uint32_t c = c0 + u * L;
-                    if (c < S.chunks) {
-                        if (c0 != ln) {  // later batches: rows not issued yet
-                            pv[u] = Store::load(prow_ptr, c);
-                            xv[u] = Store::load(xsrc, c);
-                        }
-                        gv[u] = STAGE ? Store::load(lg, c) : Store::load(grow_ptr, c);
-                    }
-                }
+        // Software pipeline: the next chunk's rows are requested before this
+        // chunk is computed.
+        for (uint32_t c = ln; c < S.chunks; c += L) {
+            // The last iteration re-reads its own chunk (in bounds, unused),
+            // so the load is unconditional and no register copies are needed.
+            const uint32_t cn = (c + L < S.chunks) ? c + L : c;
+            const T pc = Store::unpack(pr), xc = Store::unpack(xr);
+            if (!INIT) {
+                pr = Store::load_raw(prow_ptr, cn);
+                xr = Store::load_raw(xsrc, cn);
             }
-#pragma unroll
-            for (int u = 0; u < kInFlight; ++u) {
-                const uint32_t c = c0 + u * L;
-                if (c < S.chunks) {
-                    const uint4 k = words4(S, c, i, t);
-                    T xn;
-                    if constexpr (INIT)
-                        xn = Store::init(S, k);
-                    else
-                        xn = Store::template select<EQ21>(S, k, gv[u], pv[u], xv[u]);
-                    Store::store(xrow_ptr, c, xn);
-                    const f4 sv = STAGE ? ls[c] : s4[c];
-                    const f4 wv = (KIND == OBJ_RIPPLE) ? (STAGE ? lw[c] : w4[c]) : zero;
-                    const f4 xf = Store::value(S, xn);
-                    if constexpr (RAGGED)
-                        acc += terms4<KIND>(xf, sv, wv, 4u * c, S.d);
-                    else
-                        acc += terms4_full<KIND>(xf, sv, wv);
-                }
+            const uint4 k = words4(S, c, i, t);
+            T xn;
+            if constexpr (INIT) {
+                xn = Store::init(S, k);
+            } else {
+                const T g = STAGE ? Store::load(lg, c) : Store::load(grow_ptr, c);
+                xn = Store::template select<EQ21>(S, k, g, pc, xc);
             }
+            Store::store(xrow_ptr, c, xn);
+            const f4 sv = STAGE ? ls[c] : s4[c];
+            const f4 wv = (KIND == OBJ_RIPPLE) ? (STAGE ? lw[c] : w4[c]) : zero;
+            const f4 xf = Store::value(S, xn);
+            if constexpr (RAGGED)
+                acc += terms4<KIND>(xf, sv, wv, 4u * c, S.d);
+            else
+                acc += terms4_full<KIND>(xf, sv, wv);
         }
     }
     // Butterfly over the L lanes of the particle (the masks are immediates;
