@@ -107,6 +107,12 @@ def _load():
     lib.orc_set_state.restype = None
     lib.orc_argmin.argtypes = [u32, P]
     lib.orc_argmin.restype = u32
+    lib.orc_dense_f64.argtypes = [u32, P, P, P]
+    lib.orc_dense_f64.restype = f64
+    lib.orc_dense_grad.argtypes = [u32, P, P, P, P]
+    lib.orc_dense_grad.restype = None
+    lib.orc_polish.argtypes = [ctypes.POINTER(_Swarm), u32, f64]
+    lib.orc_polish.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -181,6 +187,22 @@ def fitness(kind, x, s, w=None, a=None):
     return lib.orc_fitness(kind, d, _ptr(x), _ptr(s), _ptr(_f32(w)), _ptr(_f32(a)))
 
 
+def dense_f64(x, s, a):
+    """DENSE objective at an FP64 point (FP32 s and A)."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return lib.orc_dense_f64(x.shape[0], _ptr(x), _ptr(_f32(s)), _ptr(_f32(a)))
+
+
+def dense_grad(x, s, a):
+    """Gradient 2 A^T A (x - s) of the DENSE objective at an FP64 point."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros(x.shape[0], np.float64)
+    lib.orc_dense_grad(x.shape[0], _ptr(x), _ptr(_f32(s)), _ptr(_f32(a)), _ptr(out))
+    return out
+
+
 def argmin(fp):
     lib = _load()
     fp = _f32(fp)
@@ -243,6 +265,14 @@ class Swarm:
     def run(self, generations):
         self._lib.orc_run(self._sw, generations)
         return self
+
+    def polish(self, steps, lr):
+        """Gradient polish of every pBest (DENSE swarms); returns the number
+        of replaced pBests."""
+        r = self._lib.orc_polish(self._sw, steps, lr)
+        if r < 0:
+            raise ValueError("polish needs a DENSE swarm")
+        return r
 
     def set_state(self, x, p, fp, t):
         x = _f32(x).reshape(self.n, self.d)

@@ -170,16 +170,8 @@ double orc_fitness(int kind, uint32_t d, const float *x, const float *s, const f
         }
         f = pairwise(t, d) + 0.5 * pairwise(u, d);
     } else if (kind == ORC_DENSE) {
-        /* y_k = sum_j A_kj (x_j - s_j);  f = sum_k y_k^2 */
-        double *y = (double *)malloc(sizeof(double) * (d ? d : 1));
-        for (uint32_t k = 0; k < d; ++k) {
-            for (uint32_t j = 0; j < d; ++j)
-                t[j] = (double)a[(size_t)k * d + j] * ((double)x[j] - (double)s[j]);
-            double yk = pairwise(t, d);
-            y[k] = yk * yk;
-        }
-        f = pairwise(y, d);
-        free(y);
+        for (uint32_t j = 0; j < d; ++j) t[j] = (double)x[j];
+        f = orc_dense_f64(d, t, s, a);
     } else {
         f = NAN;
     }
@@ -191,6 +183,43 @@ double orc_fitness(int kind, uint32_t d, const float *x, const float *s, const f
 /* ---------------------------------------------------------------------------
  * Swarm.
  * ------------------------------------------------------------------------- */
+/* y = A (x - s), y_k summed pairwise over j. */
+static void dense_residual(uint32_t d, const double *x, const float *s, const float *a, double *y)
+{
+    double *t = (double *)malloc(sizeof(double) * (d ? d : 1));
+    for (uint32_t k = 0; k < d; ++k) {
+        for (uint32_t j = 0; j < d; ++j)
+            t[j] = (double)a[(size_t)k * d + j] * (x[j] - (double)s[j]);
+        y[k] = pairwise(t, d);
+    }
+    free(t);
+}
+
+double orc_dense_f64(uint32_t d, const double *x, const float *s, const float *a)
+{
+    /* y_k = sum_j A_kj (x_j - s_j);  f = sum_k y_k^2 */
+    double *y = (double *)malloc(sizeof(double) * (d ? d : 1));
+    dense_residual(d, x, s, a, y);
+    for (uint32_t k = 0; k < d; ++k) y[k] = y[k] * y[k];
+    const double f = pairwise(y, d);
+    free(y);
+    return f;
+}
+
+void orc_dense_grad(uint32_t d, const double *x, const float *s, const float *a, double *out)
+{
+    /* df/dx_j = 2 sum_k A_kj y_k */
+    double *y = (double *)malloc(sizeof(double) * (d ? d : 1));
+    double *t = (double *)malloc(sizeof(double) * (d ? d : 1));
+    dense_residual(d, x, s, a, y);
+    for (uint32_t j = 0; j < d; ++j) {
+        for (uint32_t k = 0; k < d; ++k) t[k] = (double)a[(size_t)k * d + j] * y[k];
+        out[j] = 2.0 * pairwise(t, d);
+    }
+    free(t);
+    free(y);
+}
+
 static float *dup_floats(const float *src, size_t n)
 {
     if (!src) return NULL;
@@ -356,4 +385,46 @@ void orc_set_state(orc_swarm *sw, const float *x, const float *p, const float *f
     }
     update_gbest(sw);
     sw->t = t;
+}
+
+int orc_polish(orc_swarm *sw, uint32_t steps, double lr)
+{
+    if (sw->kind != ORC_DENSE) return -1;
+    const uint32_t d = sw->d;
+    const double lo = sw->rule.lo, hi = (double)(sw->rule.lo + sw->rule.span);
+    double *p = (double *)malloc(sizeof(double) * d);
+    double *g = (double *)malloc(sizeof(double) * d);
+    float *q = (float *)malloc(sizeof(float) * d);
+    int replaced = 0;
+    for (uint32_t i = 0; i < sw->n; ++i) {
+        float *pi = sw->p + (size_t)i * d;
+        for (uint32_t j = 0; j < d; ++j) q[j] = pi[j];
+        for (uint32_t k = 0; k < steps; ++k) {
+            for (uint32_t j = 0; j < d; ++j) p[j] = (double)q[j];
+            orc_dense_grad(d, p, sw->s, sw->a, g);
+            for (uint32_t j = 0; j < d; ++j) {
+                double v = p[j] - lr * g[j];
+                if (v < lo) v = lo;
+                if (v > hi) v = hi;
+                q[j] = (float)v;
+            }
+        }
+        const double f64 = orc_fitness(ORC_DENSE, d, q, sw->s, sw->w, sw->a);
+        const float f32 = (float)f64;
+        sw->fx64[i] = f64;
+        sw->improved[i] = 0;
+        const int better = less_f32(f32, sw->fp[i]);
+        if (better) {
+            for (uint32_t j = 0; j < d; ++j) pi[j] = q[j];
+            sw->fp[i] = f32;
+            sw->fp64[i] = f64;
+            sw->improved[i] = 1;
+            ++replaced;
+        }
+    }
+    update_gbest(sw);
+    free(q);
+    free(g);
+    free(p);
+    return replaced;
 }

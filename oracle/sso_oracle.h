@@ -73,6 +73,14 @@ float orc_fresh_value(const orc_rule *r, uint32_t word);
 double orc_fitness(int kind, uint32_t d, const float *x, const float *s, const float *w,
                    const float *a);
 
+/* DENSE objective at an FP64 point: f = sum_k (sum_j A_kj (x_j - s_j))^2,
+ * every sum pairwise (the same sums orc_fitness forms for FP32 points). */
+double orc_dense_f64(uint32_t d, const double *x, const float *s, const float *a);
+
+/* Its gradient at an FP64 point: g = 2 A^T y with y = A (x - s), every sum
+ * pairwise.  out[d]. */
+void orc_dense_grad(uint32_t d, const double *x, const float *s, const float *a, double *out);
+
 /* One swarm. */
 typedef struct {
     uint32_t n, d;
@@ -111,6 +119,16 @@ void orc_run(orc_swarm *sw, uint32_t generations);
  * fp64 is recomputed from p; fp is taken as given; gBest is re-derived. */
 void orc_set_state(orc_swarm *sw, const float *x, const float *p, const float *fp,
                    uint64_t t);
+
+/* Gradient polish of every pBest of a DENSE swarm (an extension outside the
+ * paper): `steps` times p <- fl32(clip(p - lr * grad f(p), lo, hi)), the
+ * gradient taken in FP64 at the FP32 point and the box [lo, hi] the swarm's.
+ * The polished point replaces the pBest iff its fitness, rounded to FP32, is
+ * below the pBest's (the rule of Algorithm 3); positions X are unchanged.
+ * gBest is re-derived.  improved[i] = 1 for each replaced pBest, fx64[i] the
+ * FP64 fitness of particle i's polished point.  Returns -1 for a swarm whose
+ * objective is not DENSE, else the number of replaced pBests. */
+int orc_polish(orc_swarm *sw, uint32_t steps, double lr);
 
 /* Index of the smallest fp (NaN above everything), lowest index on ties. */
 uint32_t orc_argmin(uint32_t n, const float *fp);

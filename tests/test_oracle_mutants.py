@@ -15,7 +15,8 @@ from oracle.build import build
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "sso_oracle.c")
 PINS = ["tests/test_oracle_philox.py", "tests/test_oracle_rule.py",
-        "tests/test_oracle_objectives.py", "tests/test_oracle_swarm.py"]
+        "tests/test_oracle_objectives.py", "tests/test_oracle_swarm.py",
+        "tests/test_oracle_gradient.py"]
 
 MUTANTS = {
     "philox multipliers swapped": (
@@ -38,8 +39,18 @@ MUTANTS = {
     "ripple sine factor dropped": ("double sn = sin(3.0 * dj);", "double sn = sin(dj);"),
     "ripple half dropped": ("f = pairwise(t, d) + 0.5 * pairwise(u, d);",
                             "f = pairwise(t, d) + pairwise(u, d);"),
-    "dense matrix transposed": ("t[j] = (double)a[(size_t)k * d + j] * ((double)x[j] - (double)s[j]);",
-                                "t[j] = (double)a[(size_t)j * d + k] * ((double)x[j] - (double)s[j]);"),
+    "dense matrix transposed": ("t[j] = (double)a[(size_t)k * d + j] * (x[j] - (double)s[j]);",
+                                "t[j] = (double)a[(size_t)j * d + k] * (x[j] - (double)s[j]);"),
+    "gradient without the factor 2": ("out[j] = 2.0 * pairwise(t, d);", "out[j] = pairwise(t, d);"),
+    "gradient through A instead of its transpose": (
+        "for (uint32_t k = 0; k < d; ++k) t[k] = (double)a[(size_t)k * d + j] * y[k];",
+        "for (uint32_t k = 0; k < d; ++k) t[k] = (double)a[(size_t)j * d + k] * y[k];"),
+    "polish step uphill": ("double v = p[j] - lr * g[j];", "double v = p[j] + lr * g[j];"),
+    "polish leaves the box": ("                if (v < lo) v = lo;\n                if (v > hi) v = hi;\n", ""),
+    "polish keeps every point": ("        if (better) {", "        if (1) {"),
+    "polish gradient frozen at the first point": (
+        "            for (uint32_t j = 0; j < d; ++j) p[j] = (double)q[j];\n            orc_dense_grad(d, p, sw->s, sw->a, g);",
+        "            if (k == 0) {\n                for (uint32_t j = 0; j < d; ++j) p[j] = (double)q[j];\n                orc_dense_grad(d, p, sw->s, sw->a, g);\n            }"),
     "pBest replaced on ties": ("if (less_f32(f32, sw->fp[i])) {", "if (!less_f32(sw->fp[i], f32)) {"),
     "gBest ties to the highest index": ("if (less_f32(fp[i], fp[best])) best = i;",
                                         "if (!less_f32(fp[best], fp[i])) best = i;"),
