@@ -99,6 +99,11 @@ typedef struct {
     const float *s;      /* host [d]: shift (optimum)                             */
     const float *w;      /* host [d]: RIPPLE weights, else ignored (may be NULL)  */
     const float *a;      /* host [d*d] row-major: DENSE matrix, else ignored      */
+    uint32_t polish_every; /* DENSE only: 0 = off; else after every generation t
+                              with t mod polish_every == 0, sso_run applies
+                              sso_polish(polish_steps, polish_lr)               */
+    uint32_t polish_steps; /* gradient steps per polish (used when polish_every) */
+    float    polish_lr;    /* step size; <= 0 means 0.05 / sigma_max(A)^2        */
 } sso_config;
 
 typedef struct sso_ctx sso_ctx;
@@ -150,6 +155,29 @@ int sso_get_trace(sso_ctx *ctx, uint64_t first, uint32_t count, float *fg,
  * generation t to dev_words[i*d + j] (device memory, n*d uint32), with the
  * same generator and counter layout the kernels use. */
 int sso_debug_rng(sso_ctx *ctx, uint64_t t, uint32_t *dev_words);
+
+/* ------------------------------------------------------------------------
+ * Differentiation (DENSE contexts; the objective is ||A (x - s)||^2, whose
+ * gradient is 2 A^T A (x - s)).  Not part of the paper's method: an optional
+ * gradient polish of the pBests beside plain SSO.
+ * ------------------------------------------------------------------------ */
+
+/* Enqueue, for m points x (device [m*d], row-major, FP32): f_out[i] = f(x_i)
+ * (device [m], may be NULL) and grad_out[i*d + j] = gout[i] * df/dx_j at x_i
+ * (device [m*d], may be NULL; gout device [m] or NULL for 1).  Uses the
+ * context's s and A and its stream; the swarm state is not touched.
+ * SSO_E_UNSUPPORTED for a non-DENSE context. */
+int sso_eval(sso_ctx *ctx, const float *dev_x, uint32_t m, const float *dev_gout,
+             float *f_out, float *grad_out);
+
+/* Enqueue a gradient polish of every pBest: `steps` projected steps
+ * p <- clip(p - lr * grad f(p), lo, hi) in FP32; a polished point replaces
+ * the pBest iff its fitness is strictly lower (Algorithm 3's rule), the
+ * current positions are unchanged, and gBest of the current generation is
+ * re-derived.  lr <= 0 selects 0.05 / sigma_max(A)^2 (sigma_max from an FP64
+ * power iteration on the host at sso_init); *lr_used (host, may be NULL)
+ * receives the step size.  SSO_E_UNSUPPORTED for a non-DENSE context. */
+int sso_polish(sso_ctx *ctx, uint32_t steps, float lr, float *lr_used);
 
 /* Free the context (not the workspace).  NULL is allowed. */
 void sso_destroy(sso_ctx *ctx);

@@ -48,6 +48,9 @@ class Config(ctypes.Structure):
         ("s", ctypes.c_void_p),
         ("w", ctypes.c_void_p),
         ("a", ctypes.c_void_p),
+        ("polish_every", ctypes.c_uint32),
+        ("polish_steps", ctypes.c_uint32),
+        ("polish_lr", ctypes.c_float),
     ]
 
 
@@ -74,6 +77,8 @@ def load():
         "sso_set_state": (ctypes.c_int, [P, P, P, P, u64]),
         "sso_get_trace": (ctypes.c_int, [P, u64, u32, P, P, P]),
         "sso_debug_rng": (ctypes.c_int, [P, u64, P]),
+        "sso_eval": (ctypes.c_int, [P, P, u32, P, P, P]),
+        "sso_polish": (ctypes.c_int, [P, u32, ctypes.c_float, P]),
         "sso_destroy": (None, [P]),
         "sso_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sso_last_error": (ctypes.c_char_p, [P]),
@@ -107,7 +112,8 @@ def _f32(a):
 
 
 def make_config(n, d, kind, lo, hi, cg, cp, cw, seed, s, w=None, a=None, swarm_id=0,
-                order=ORDER_GPS, engine="auto", lanes=0, trace_cap=0, storage="auto"):
+                order=ORDER_GPS, engine="auto", lanes=0, trace_cap=0, storage="auto",
+                polish_every=0, polish_steps=0, polish_lr=0.0):
     """Returns (Config, keepalive) with host arrays pinned in `keepalive`."""
     s, w, a = _f32(s), _f32(w), _f32(a)
     cfg = Config(n=n, d=d, lo=lo, hi=hi, cg=cg, cp=cp, cw=cw, seed=seed, swarm_id=swarm_id,
@@ -116,7 +122,8 @@ def make_config(n, d, kind, lo, hi, cg, cp, cw, seed, s, w=None, a=None, swarm_i
                  storage=STORAGE[storage] if isinstance(storage, str) else storage, lanes=lanes,
                  trace_cap=trace_cap, s=s.ctypes.data if s is not None else None,
                  w=w.ctypes.data if w is not None else None,
-                 a=a.ctypes.data if a is not None else None)
+                 a=a.ctypes.data if a is not None else None, polish_every=polish_every,
+                 polish_steps=polish_steps, polish_lr=polish_lr)
     return cfg, (s, w, a)
 
 
@@ -134,13 +141,14 @@ class Swarm:
 
     def __init__(self, n, d, kind, lo, hi, cg, cp, cw, seed, s, w=None, a=None, swarm_id=0,
                  order=ORDER_GPS, engine="auto", lanes=0, trace_cap=0, storage="auto",
-                 device="cuda", stream=None):
+                 polish_every=0, polish_steps=0, polish_lr=0.0, device="cuda", stream=None):
         import torch
 
         self._lib = load()
         self.n, self.d = n, d
         self._cfg, self._keep = make_config(n, d, kind, lo, hi, cg, cp, cw, seed, s, w, a,
-                                            swarm_id, order, engine, lanes, trace_cap, storage)
+                                            swarm_id, order, engine, lanes, trace_cap, storage,
+                                            polish_every, polish_steps, polish_lr)
         nbytes = workspace_bytes(self._cfg)
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -210,6 +218,41 @@ class Swarm:
         im = np.zeros(count, np.uint32)
         self._check(self._lib.sso_get_trace(self._ctx, first, count, _ptr(fg), _ptr(gi), _ptr(im)))
         return fg, gi, im
+
+    def polish(self, steps, lr=0.0):
+        """Gradient polish of every pBest (DENSE); returns the step size used."""
+        used = ctypes.c_float()
+        self._check(self._lib.sso_polish(self._ctx, steps, lr, ctypes.byref(used)))
+        return float(used.value)
+
+    def eval(self, x, gout=None, f=True, grad=False):
+        """f and/or gout * grad f at the rows of x (an (m, d) float32 device
+        tensor), computed by the library's kernels on this swarm's stream.
+        Returns (f or None, grad or None) as device tensors."""
+        import torch
+
+        if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != self.d or not x.is_cuda:
+            raise ValueError("x must be an (m, d) float32 GPU tensor")
+        x = x.contiguous()
+        m = x.shape[0]
+        fo = torch.empty(m, dtype=torch.float32, device=x.device) if f else None
+        go = torch.empty_like(x) if grad else None
+        if gout is not None:
+            gout = gout.to(dtype=torch.float32).contiguous()
+            if gout.shape != (m,):
+                raise ValueError("gout must have shape (m,)")
+        cur = torch.cuda.current_stream(x.device)
+        self.stream.wait_stream(cur)
+        self._check(self._lib.sso_eval(
+            self._ctx, ctypes.c_void_p(x.data_ptr()), m,
+            ctypes.c_void_p(gout.data_ptr()) if gout is not None else None,
+            ctypes.c_void_p(fo.data_ptr()) if fo is not None else None,
+            ctypes.c_void_p(go.data_ptr()) if go is not None else None))
+        cur.wait_stream(self.stream)
+        for tns in (x, gout, fo, go):
+            if tns is not None:
+                tns.record_stream(self.stream)
+        return fo, go
 
     def debug_rng(self, t):
         """The device's Philox words of generation t, as an [n, d] uint32 array."""
@@ -360,3 +403,43 @@ class _BatchSwarm:
         self._check(lib.sso_batch_get_trace(ctx, self.k, first, count, _ptr(fg), _ptr(gi),
                                             _ptr(im)))
         return fg, gi, im
+
+
+def dense_objective(x, swarm):
+    """f(x) = ||A (x_i - s)||^2 for the rows of x, differentiable in x: the
+    forward and the backward pass (2 A^T A (x - s) times the incoming
+    gradient) run in the library's MFMA kernels (sso_eval)."""
+    return _DenseObjective.apply(x, swarm)
+
+
+def _make_dense_objective():
+    import torch
+
+    class DenseObjective(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, swarm):
+            f, _ = swarm.eval(x, f=True, grad=False)
+            ctx.save_for_backward(x)
+            ctx.swarm = swarm
+            return f
+
+        @staticmethod
+        def backward(ctx, gout):
+            (x,) = ctx.saved_tensors
+            _, gx = ctx.swarm.eval(x, gout=gout, f=False, grad=True)
+            return gx, None
+
+    return DenseObjective
+
+
+class _LazyFunction:
+    def __init__(self):
+        self._fn = None
+
+    def apply(self, *args):
+        if self._fn is None:
+            self._fn = _make_dense_objective()
+        return self._fn.apply(*args)
+
+
+_DenseObjective = _LazyFunction()

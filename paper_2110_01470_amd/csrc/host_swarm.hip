@@ -136,6 +136,9 @@ int validate(const sso_config *c, std::string *why)
         return bad(SSO_E_INVAL, "fresh interval must hold more than 2^24 words (1 - last threshold > 2^-8)");
     if (c->engine == SSO_ENGINE_RESIDENT && !resident_fits(c->n, c->d, c->kind))
         return bad(SSO_E_UNSUPPORTED, "swarm does not fit the resident engine (one workgroup, separable objective)");
+    if (c->polish_every != 0 && c->kind != SSO_OBJ_DENSE)
+        return bad(SSO_E_UNSUPPORTED, "the gradient polish needs the dense objective");
+    if (!(c->polish_lr == c->polish_lr) || std::isinf(c->polish_lr)) return bad(SSO_E_INVAL, "polish_lr must be finite");
     if (c->storage < SSO_STORAGE_AUTO || c->storage > SSO_STORAGE_U24) return bad(SSO_E_INVAL, "unknown storage");
     if (c->storage == SSO_STORAGE_U24) {
         int e, st;

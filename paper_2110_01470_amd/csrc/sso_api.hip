@@ -23,6 +23,11 @@ struct sso_ctx {
     uint32_t lanes;    // STREAM lanes per particle
     uint64_t t;        // generations done
     uint64_t trace_base;
+    // DENSE: the matrix (host, row-major) for sigma_max, and the polish schedule.
+    std::vector<float> a_host;
+    double sigma_max = 0.0;  // 0 until first needed
+    uint32_t polish_every = 0, polish_steps = 0;
+    float polish_lr = 0.0f;
     std::string err;
 };
 
@@ -33,7 +38,7 @@ using namespace sso::host;
 thread_local std::string g_err;
 
 struct Layout {
-    size_t rows, fp, st, s, w, a, keys, cnt, sub, total;
+    size_t rows, fp, st, s, w, a, at, keys, cnt, sub, total;
     uint32_t dp, stride, trace_cap;
     int engine, storage;
 };
@@ -52,6 +57,7 @@ Layout make_layout(const sso_config &c)
     L.s = off;    off += align256((size_t)L.dp * sizeof(float));
     L.w = off;    off += c.kind == SSO_OBJ_RIPPLE ? align256((size_t)L.dp * sizeof(float)) : 0;
     L.a = off;    off += c.kind == SSO_OBJ_DENSE ? align256(dense_matrix_floats(c.d) * sizeof(float)) : 0;
+    L.at = off;   off += c.kind == SSO_OBJ_DENSE ? align256(dense_matrix_floats(c.d) * sizeof(float)) : 0;
     L.keys = off; off += align256((size_t)L.trace_cap * sizeof(unsigned long long));
     L.cnt = off;  off += align256((size_t)L.trace_cap * sizeof(uint32_t));
     L.sub = off;  off += align256((size_t)kSubWords * sizeof(unsigned long long));
@@ -72,6 +78,50 @@ uint32_t stream_lanes(uint32_t d, int storage)
     return L;
 }
 
+// Largest singular value of the DENSE matrix: power iteration on A^T A in
+// FP64 from the all-ones vector; the Rayleigh quotient ||A v||^2 converges
+// monotonically from below.  Run once, when a default step size is needed.
+double sigma_max(sso_ctx *ctx)
+{
+    if (ctx->sigma_max > 0.0) return ctx->sigma_max;
+    const uint32_t d = ctx->S.d;
+    const std::vector<float> &a = ctx->a_host;
+    std::vector<double> v(d, 1.0 / std::sqrt((double)d)), y(d), w(d);
+    double lam = 0.0;
+    for (int it = 0; it < 5000; ++it) {
+        for (uint32_t k = 0; k < d; ++k) {
+            double acc = 0.0;
+            for (uint32_t j = 0; j < d; ++j) acc += (double)a[(size_t)k * d + j] * v[j];
+            y[k] = acc;
+        }
+        double ny = 0.0;
+        for (uint32_t k = 0; k < d; ++k) ny += y[k] * y[k];
+        for (uint32_t j = 0; j < d; ++j) {
+            double acc = 0.0;
+            for (uint32_t k = 0; k < d; ++k) acc += (double)a[(size_t)k * d + j] * y[k];
+            w[j] = acc;
+        }
+        double nw = 0.0;
+        for (uint32_t j = 0; j < d; ++j) nw += w[j] * w[j];
+        nw = std::sqrt(nw);
+        const double prev = lam;
+        lam = ny;  // v has unit norm: v^T A^T A v
+        if (nw == 0.0) break;
+        for (uint32_t j = 0; j < d; ++j) v[j] = w[j] / nw;
+        if (it > 0 && std::fabs(lam - prev) <= 1e-15 * lam) break;
+    }
+    ctx->sigma_max = std::sqrt(lam);
+    return ctx->sigma_max;
+}
+
+// The polish step size: lr, or 0.05 / sigma_max^2 when lr <= 0.
+float polish_step_size(sso_ctx *ctx, float lr)
+{
+    if (lr > 0.0f) return lr;
+    const double s = sigma_max(ctx);
+    return s > 0.0 ? (float)(0.05 / (s * s)) : 0.0f;
+}
+
 int launch_generations(sso_ctx *ctx, uint64_t t_first, uint32_t count)
 {
     const SwarmDev &S = ctx->S;
@@ -80,11 +130,16 @@ int launch_generations(sso_ctx *ctx, uint64_t t_first, uint32_t count)
         if (e) return hip_fail(&ctx->err, (hipError_t)e, "resident kernel launch");
         return SSO_OK;
     }
+    const float lr = ctx->polish_every ? polish_step_size(ctx, ctx->polish_lr) : 0.0f;
     for (uint32_t k = 0; k < count; ++k) {
         const uint32_t t = (uint32_t)(t_first + k);
-        const int e = S.kind == SSO_OBJ_DENSE ? launch_dense_generation(S, t, ctx->stream)
-                                              : launch_stream_generation(S, t, ctx->lanes, ctx->stream);
+        int e = S.kind == SSO_OBJ_DENSE ? launch_dense_generation(S, t, ctx->stream)
+                                        : launch_stream_generation(S, t, ctx->lanes, ctx->stream);
         if (e) return hip_fail(&ctx->err, (hipError_t)e, "generation kernel launch");
+        if (ctx->polish_every && t % ctx->polish_every == 0) {
+            e = launch_dense_polish(S, ctx->polish_steps, lr, t, ctx->stream);
+            if (e) return hip_fail(&ctx->err, (hipError_t)e, "polish kernel launch");
+        }
     }
     return SSO_OK;
 }
@@ -164,6 +219,7 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
     S.s = (const float *)(base + L.s);
     S.w = cfg->kind == SSO_OBJ_RIPPLE ? (const float *)(base + L.w) : nullptr;
     S.a = cfg->kind == SSO_OBJ_DENSE ? (const float *)(base + L.a) : nullptr;
+    S.at = cfg->kind == SSO_OBJ_DENSE ? (const float *)(base + L.at) : nullptr;
     S.keys = (unsigned long long *)(base + L.keys);
     S.cnt = (uint32_t *)(base + L.cnt);
     S.sub = (unsigned long long *)(base + L.sub);
@@ -186,13 +242,26 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
     };
     rc = upload_separable(*cfg, S, ctx->stream, err);
     if (rc != SSO_OK) return fail(rc);
-    std::vector<float> apack;
+    std::vector<float> apack, atpack;
     if (cfg->kind == SSO_OBJ_DENSE) {
-        apack.assign(dense_matrix_floats(cfg->d), 0.0f);
-        dense_pack_matrix(cfg->a, cfg->d, apack.data());
-        const hipError_t e = hipMemcpyAsync((void *)S.a, apack.data(), sizeof(float) * apack.size(),
-                                            hipMemcpyHostToDevice, ctx->stream);
+        const uint32_t d = cfg->d;
+        ctx->a_host.assign(cfg->a, cfg->a + (size_t)d * d);
+        std::vector<float> at((size_t)d * d);
+        for (uint32_t k = 0; k < d; ++k)
+            for (uint32_t j = 0; j < d; ++j) at[(size_t)j * d + k] = cfg->a[(size_t)k * d + j];
+        apack.assign(dense_matrix_floats(d), 0.0f);
+        atpack.assign(dense_matrix_floats(d), 0.0f);
+        dense_pack_matrix(cfg->a, d, apack.data());
+        dense_pack_matrix(at.data(), d, atpack.data());
+        hipError_t e = hipMemcpyAsync((void *)S.a, apack.data(), sizeof(float) * apack.size(),
+                                      hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((void *)S.at, atpack.data(), sizeof(float) * atpack.size(),
+                               hipMemcpyHostToDevice, ctx->stream);
         if (e != hipSuccess) return fail(hip_fail(err, e, "upload a"));
+        ctx->polish_every = cfg->polish_every;
+        ctx->polish_steps = cfg->polish_steps;
+        ctx->polish_lr = cfg->polish_lr;
     }
     const hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return fail(hip_fail(err, e, "synchronise uploads"));
@@ -270,6 +339,52 @@ int sso_debug_rng(sso_ctx *ctx, uint64_t t, uint32_t *dev_words)
     }
     const int e = launch_debug_rng(ctx->S, (uint32_t)t, dev_words, ctx->stream);
     if (e) return hip_fail(&ctx->err, (hipError_t)e, "debug rng launch");
+    return SSO_OK;
+}
+
+int sso_eval(sso_ctx *ctx, const float *dev_x, uint32_t m, const float *dev_gout, float *f_out,
+             float *grad_out)
+{
+    if (!ctx) return SSO_E_INVAL;
+    if (ctx->S.kind != SSO_OBJ_DENSE) {
+        ctx->err = "sso_eval needs the dense objective";
+        return SSO_E_UNSUPPORTED;
+    }
+    if (m && !dev_x) {
+        ctx->err = "x is NULL";
+        return SSO_E_INVAL;
+    }
+    if (m >= (1u << 31)) {
+        ctx->err = "m must be below 2^31";
+        return SSO_E_UNSUPPORTED;
+    }
+    GradArgs G{};
+    G.x = dev_x;
+    G.gout = dev_gout;
+    G.f = f_out;
+    G.g = grad_out;
+    G.m = m;
+    G.ld = ctx->S.d;
+    const int e = launch_dense_eval(ctx->S, G, ctx->stream);
+    if (e) return hip_fail(&ctx->err, (hipError_t)e, "dense eval launch");
+    return SSO_OK;
+}
+
+int sso_polish(sso_ctx *ctx, uint32_t steps, float lr, float *lr_used)
+{
+    if (!ctx) return SSO_E_INVAL;
+    if (ctx->S.kind != SSO_OBJ_DENSE) {
+        ctx->err = "sso_polish needs the dense objective";
+        return SSO_E_UNSUPPORTED;
+    }
+    if (!(lr == lr) || std::isinf(lr)) {
+        ctx->err = "lr must be finite";
+        return SSO_E_INVAL;
+    }
+    const float step = polish_step_size(ctx, lr);
+    const int e = launch_dense_polish(ctx->S, steps, step, (uint32_t)ctx->t, ctx->stream);
+    if (e) return hip_fail(&ctx->err, (hipError_t)e, "polish kernel launch");
+    if (lr_used) *lr_used = step;
     return SSO_OK;
 }
 

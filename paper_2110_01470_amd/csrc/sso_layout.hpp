@@ -59,6 +59,7 @@ struct SwarmDev {
     const float *s;              // [dp] shift, zero padded
     const float *w;              // [dp] ripple weights, zero padded (or null)
     const float *a;              // dense matrix, layout of the dense kernel (or null)
+    const float *at;             // its transpose in the same layout (dense only)
     unsigned long long *keys;    // [trace_cap] gBest key per finished generation (ring)
     uint32_t *cnt;               // [trace_cap] improved pBests per finished generation (ring)
     unsigned long long *sub;     // [kGroups][kSubSlots][kSubStride]: key, then count
@@ -111,5 +112,19 @@ int batch_graph(const BatchDev &B, uint32_t k, void **graph_out);
 int launch_batch_collect(const BatchDev &B, uint32_t t, void *stream);
 size_t batch_stage_bytes(int kind, int storage, uint32_t chunks);
 void dense_pack_matrix(const float *a, uint32_t d, float *out);
+
+// Dense objective at given points and its gradient (grad_dense.hip).
+struct GradArgs {
+    const float *x;     // [m][ld] points (device)
+    const float *gout;  // [m] factors of the gradients, or null (1)
+    float *f;           // [m] f(x), or null
+    float *g;           // [m][ld] gout * grad f(x), or null
+    uint32_t m, ld;
+};
+// f and/or gradients at m points; S supplies s, a, at and d.
+int launch_dense_eval(const SwarmDev &S, const GradArgs &G, void *stream);
+// Gradient polish of every pBest of the swarm (steps projected steps of
+// size lr, accept-if-better); new gBest keys go to generation t's group.
+int launch_dense_polish(const SwarmDev &S, uint32_t steps, float lr, uint32_t t, void *stream);
 
 }  // namespace sso

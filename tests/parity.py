@@ -38,6 +38,7 @@ class Pair:
         from paper_2110_01470_amd.binding import Swarm
 
         self.kind, self.n, self.d = kind, n, d
+        self.lo, self.hi = lo, hi
         if objective is None:
             objective = make_objective(kind, d, seed, *s_range)
         self.s, self.w, self.a = objective

@@ -22,9 +22,10 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("sso_init", "sso_step", "sso_run", "sso_get_best", "sso_batch_init",
-                     "sso_batch_run", "sso_batch_tune", "sso_batch_get_results"):
+                     "sso_batch_run", "sso_batch_tune", "sso_batch_get_results", "sso_eval",
+                     "sso_polish"):
         assert required in names
-    assert len(names) == 24
+    assert len(names) == 26
 
 
 def test_library_exports_every_declared_symbol():
@@ -66,6 +67,8 @@ def test_workspace_bytes_for_valid_configs():
     dict(kind="dense", d=257, a=np.eye(257, dtype=np.float32)),
     dict(engine="resident", n=2000), dict(lo=-3e38, hi=3e38),
     dict(storage=7), dict(storage="u24", engine="resident"),
+    dict(polish_every=50, polish_steps=5), dict(kind="ripple", w=np.ones(30, np.float32), polish_every=1),
+    dict(kind="dense", a=np.eye(30, dtype=np.float32), polish_lr=float("nan")),
     dict(storage="u24", kind="dense", a=np.eye(30, dtype=np.float32)),
 ])
 def test_invalid_configs_are_rejected(kw):
