@@ -26,6 +26,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -176,6 +178,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ripple_n65536_d1000",
                     choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS))
+    ap.add_argument("--polish", action="store_true",
+                    help="dense workload: time-to-gap of plain SSO vs SSO with a gradient "
+                         "polish of all pBests every 50 generations")
     ap.add_argument("--tune-gens", type=int, default=5,
                     help="generations the batch mapping tuner times per candidate")
     ap.add_argument("--engine", default="auto", choices=["auto", "stream", "resident"])
@@ -200,6 +205,9 @@ def main():
         return
 
     wl = WORKLOADS[args.workload]
+    if args.polish:
+        bench_polish(wl, args)
+        return
     steps = args.steps if args.steps is not None else wl.generations
     log(f"workload {wl.name}: N={wl.n} D={wl.d} steps={steps} warmup={args.warmup}")
     ms, fg, gen = time_gpu(wl, steps, args.warmup, args.engine)
@@ -255,6 +263,127 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
+
+
+POLISH_EVERY, POLISH_STEPS = 50, 5
+
+
+def time_to_gap(fg, gen_ms, polish_ms, every, gap):
+    """Milliseconds until the gBest gap fG - f* (f* = 0) first reaches `gap`:
+    generations at gen_ms each plus the polishes done by then; None if never."""
+    hit = np.nonzero(fg <= gap)[0]
+    if hit.size == 0:
+        return None
+    t = int(hit[0])
+    return t * gen_ms + ((t // every) * polish_ms if every else 0.0)
+
+
+def bench_polish(wl, args):
+    """Plain SSO against SSO with a 5-step projected-gradient polish of all
+    pBests every 50 generations (step 0.05 / sigma_max(A)^2) on the dense
+    workload: both runs timed with HIP events, the polish kernel timed on its
+    own for its MFMA rate, and the time each run needs to reach a gap."""
+    import torch
+
+    from paper_2110_01470_amd.binding import Swarm
+
+    steps = args.steps if args.steps is not None else wl.generations
+    s, w, a = wl.objective()
+    stream = torch.cuda.Stream()
+    args_ = (wl.n, wl.d, wl.kind, wl.lo, wl.hi, wl.cg, wl.cp, wl.cw, wl.seed, s, w, a)
+    runs = {}
+    for name, kw in (("plain", {}), ("polished", dict(polish_every=POLISH_EVERY,
+                                                       polish_steps=POLISH_STEPS))):
+        sw = Swarm(*args_, stream=stream, trace_cap=steps + 8, **kw)
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sw.run(steps)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        fg, _, _ = sw.trace(0, steps + 1)
+        runs[name] = {"ms": ms, "fg": fg.astype(np.float64)}
+        log(f"{name}: {ms:.1f} ms for {steps} generations, final fG {fg[-1]:.6g}")
+        sw.close()
+    # The polish kernel alone: (4 steps + 2) N D^2 FLOP per call.
+    sw = Swarm(*args_, stream=stream)
+    sw.run(10)
+    lr = sw.polish(POLISH_STEPS)
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # The stream is busy with one more polish when the timed region opens, so
+    # it holds no host launch latency.
+    sw.polish(POLISH_STEPS, lr)
+    e0.record(stream)
+    for _ in range(reps):
+        sw.polish(POLISH_STEPS, lr)
+    e1.record(stream)
+    e1.synchronize()
+    polish_ms = e0.elapsed_time(e1) / reps
+    flop = (4 * POLISH_STEPS + 2) * wl.n * wl.d * wl.d
+    tflops = flop / (polish_ms / 1e3) / 1e12
+    log(f"polish: {polish_ms * 1e3:.1f} us per call, {tflops:.1f} TFLOP/s")
+
+    plain_gen_ms = runs["plain"]["ms"] / steps
+    pol_gen_ms = (runs["polished"]["ms"] - (steps // POLISH_EVERY) * polish_ms) / steps
+    gap_target = 1e-6
+    final = {k: float(v["fg"][-1]) for k, v in runs.items()}
+    if all(final[k] <= gap_target for k in final):
+        gap = gap_target
+    else:
+        gap = max(final.values())  # the best gap both runs reach
+    ttg = {"plain": time_to_gap(runs["plain"]["fg"], plain_gen_ms, 0.0, 0, gap),
+           "polished": time_to_gap(runs["polished"]["fg"], pol_gen_ms, polish_ms, POLISH_EVERY, gap)}
+    reached = {k: time_to_gap(v["fg"], plain_gen_ms if k == "plain" else pol_gen_ms,
+                              0.0 if k == "plain" else polish_ms, 0 if k == "plain" else POLISH_EVERY,
+                              gap_target) for k, v in runs.items()}
+    rec = {
+        "metric": "time-to-gap vs plain SSO (dense objective, gradient polish every 50 generations)",
+        "value": ttg["polished"] / 1e3 if ttg["polished"] is not None else None,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": runs["polished"]["ms"] / steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name + "+polish", "objective": wl.kind, "n": wl.n, "d": wl.d,
+                   "generations": steps, "polish_every": POLISH_EVERY, "polish_steps": POLISH_STEPS,
+                   "polish_lr": lr},
+        "gap": {"target": gap_target, "compared_at": gap,
+                "time_to_target_ms": reached,
+                "time_to_compared_gap_ms": ttg,
+                "final_gap": final,
+                "speedup_vs_plain": (ttg["plain"] / ttg["polished"]
+                                     if ttg["plain"] and ttg["polished"] else None),
+                "ms_total": {k: v["ms"] for k, v in runs.items()}},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MATRIX_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / FP32_MATRIX_PEAK_TFLOPS,
+                     "traffic": None},
+        "polish_rate": {"value": wl.n / (polish_ms / 1e3), "unit": "pBests polished/s"},
+        "cpu_baseline": cpu_polish_baseline(wl, lr) if args.cpu_gens != 0 else None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def cpu_polish_baseline(wl, lr, sample=1024):
+    """The oracle's polish of `sample` pBests of the same instance."""
+    import oracle
+
+    s, w, a = wl.objective()
+    orc = oracle.Swarm(sample, wl.d, oracle.DENSE, wl.lo, wl.hi, wl.cg, wl.cp, wl.cw, wl.seed, s,
+                       None, a)
+    orc.init()
+    t0 = time.perf_counter()
+    orc.polish(POLISH_STEPS, lr)
+    sec = time.perf_counter() - t0
+    return {"value": sample / sec, "unit": "pBests polished/s", "cores": 1, "kind": "oracle",
+            "sample": f"{POLISH_STEPS}-step polish of {sample} pBests of {wl.name}, single-threaded "
+                      f"FP64 oracle, {sec:.2f} s"}
 
 
 def bench_batch(bw, args):
