@@ -27,6 +27,8 @@ import numpy as np
 from .build import LIB_PATH, build
 
 SPHERE, RIPPLE, DENSE = 0, 1, 2
+# Table 3.2's benchmark functions.
+F1, F2, F3, F4, F5, F6, F7, F8, F9 = range(11, 20)
 SRC_GBEST, SRC_PBEST, SRC_SELF, SRC_FRESH = 0, 1, 2, 3
 ORDER_GPS, ORDER_EQ21 = 0, 1
 
@@ -107,6 +109,8 @@ def _load():
     lib.orc_set_state.restype = None
     lib.orc_argmin.argtypes = [u32, P]
     lib.orc_argmin.restype = u32
+    lib.orc_fitness_scale.argtypes = [ctypes.c_int, u32, P, P, P, P]
+    lib.orc_fitness_scale.restype = f64
     lib.orc_dense_f64.argtypes = [u32, P, P, P]
     lib.orc_dense_f64.restype = f64
     lib.orc_dense_grad.argtypes = [u32, P, P, P, P]
@@ -185,6 +189,14 @@ def fitness(kind, x, s, w=None, a=None):
     s = _f32(s)
     d = x.shape[0]
     return lib.orc_fitness(kind, d, _ptr(x), _ptr(s), _ptr(_f32(w)), _ptr(_f32(a)))
+
+
+def fitness_scale(kind, x, s=None, w=None, a=None):
+    """Magnitude of the quantities the objective adds up at x (FP64)."""
+    lib = _load()
+    x = _f32(x)
+    return lib.orc_fitness_scale(kind, x.shape[0], _ptr(x), _ptr(_f32(s)), _ptr(_f32(w)),
+                                 _ptr(_f32(a)))
 
 
 def dense_f64(x, s, a):

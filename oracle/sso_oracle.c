@@ -147,6 +147,102 @@ static double pairwise(const double *v, size_t n)
     return pairwise(v, h) + pairwise(v + h, n - h);
 }
 
+/* Table 3.2.  With scale != 0 the same sums of magnitudes (see
+ * orc_fitness_scale).  t and u are scratch arrays of d doubles. */
+static double paper_function(int kind, uint32_t d, const float *x, double *t, double *u, int scale)
+{
+    const double pi = 3.14159265358979323846, e1 = 2.71828182845904523536;
+    const double P = (double)d;
+    double f = 0.0;
+    switch (kind) {
+    case ORC_F1:  /* sphere */
+        for (uint32_t i = 0; i < d; ++i) t[i] = (double)x[i] * x[i];
+        f = pairwise(t, d);
+        break;
+    case ORC_F2:  /* hyper-ellipsoid: the i-th square weighted by i (from 1) */
+        for (uint32_t i = 0; i < d; ++i) t[i] = (double)(i + 1) * x[i] * x[i];
+        f = pairwise(t, d);
+        break;
+    case ORC_F3: {  /* Schwefel 1.2: squares of the running sums */
+        double run = 0.0;
+        for (uint32_t i = 0; i < d; ++i) {
+            run += scale ? fabs((double)x[i]) : (double)x[i];
+            t[i] = run * run;
+        }
+        f = pairwise(t, d);
+        break;
+    }
+    case ORC_F4: {  /* Rosenbrock: neighbouring pairs (x_i, x_{i+1}) */
+        const uint32_t m = d ? d - 1 : 0;
+        for (uint32_t i = 0; i < m; ++i) {
+            const double xi = x[i], xn = x[i + 1];
+            const double q = scale ? fabs(xn) + xi * xi : xn - xi * xi;
+            const double r = scale ? 1.0 + fabs(xi) : 1.0 - xi;
+            t[i] = 100.0 * q * q + r * r;
+        }
+        f = pairwise(t, m);
+        break;
+    }
+    case ORC_F5:  /* Rastrigin */
+        for (uint32_t i = 0; i < d; ++i) {
+            const double c = cos(2.0 * pi * x[i]);
+            t[i] = (double)x[i] * x[i] + (scale ? 10.0 * fabs(c) : -10.0 * c);
+        }
+        f = 10.0 * P + pairwise(t, d);
+        break;
+    case ORC_F6: {  /* Ackley, a = 20, b = 0.2, c = 2 pi */
+        for (uint32_t i = 0; i < d; ++i) {
+            t[i] = (double)x[i] * x[i];
+            u[i] = cos(2.0 * pi * x[i]);
+        }
+        const double e_a = exp(-0.2 * sqrt(pairwise(t, d) / P));
+        const double e_b = exp(pairwise(u, d) / P);
+        f = scale ? 20.0 * e_a + e_b + 20.0 + e1 : -20.0 * e_a - e_b + 20.0 + e1;
+        break;
+    }
+    case ORC_F7: {  /* Griewank */
+        double prod = 1.0;
+        for (uint32_t i = 0; i < d; ++i) {
+            t[i] = (double)x[i] * x[i];
+            prod *= cos((double)x[i] / sqrt((double)(i + 1)));
+        }
+        f = scale ? pairwise(t, d) / 4000.0 + fabs(prod) + 1.0 : pairwise(t, d) / 4000.0 - prod + 1.0;
+        break;
+    }
+    case ORC_F8: {  /* Powell: groups (x1, x2, x3, x4) of four consecutive variables */
+        const uint32_t g = d / 4;
+        for (uint32_t k = 0; k < g; ++k) {
+            const double x1 = x[4 * k], x2 = x[4 * k + 1], x3 = x[4 * k + 2], x4 = x[4 * k + 3];
+            double a1, a2, a3, a4;
+            if (scale) {
+                a1 = fabs(x1) + 10.0 * fabs(x2);
+                a2 = fabs(x3) + fabs(x4);
+                a3 = fabs(x2) + 2.0 * fabs(x3);
+                a4 = fabs(x1) + fabs(x4);
+            } else {
+                a1 = x1 + 10.0 * x2;
+                a2 = x3 - x4;
+                a3 = x2 - 2.0 * x3;
+                a4 = x1 - x4;
+            }
+            t[k] = a1 * a1 + 5.0 * a2 * a2 + a3 * a3 * a3 * a3 + 10.0 * a4 * a4 * a4 * a4;
+        }
+        f = pairwise(t, g);
+        break;
+    }
+    case ORC_F9:  /* Schwefel 2.26 */
+        for (uint32_t i = 0; i < d; ++i) {
+            const double v = (double)x[i] * sin(sqrt(fabs((double)x[i])));
+            t[i] = scale ? fabs(v) : v;
+        }
+        f = scale ? 418.9829 * P + pairwise(t, d) : 418.9829 * P - pairwise(t, d);
+        break;
+    default:
+        f = NAN;
+    }
+    return f;
+}
+
 double orc_fitness(int kind, uint32_t d, const float *x, const float *s, const float *w,
                    const float *a)
 {
@@ -172,9 +268,27 @@ double orc_fitness(int kind, uint32_t d, const float *x, const float *s, const f
     } else if (kind == ORC_DENSE) {
         for (uint32_t j = 0; j < d; ++j) t[j] = (double)x[j];
         f = orc_dense_f64(d, t, s, a);
+    } else if (kind >= ORC_F1 && kind <= ORC_F9) {
+        f = paper_function(kind, d, x, t, u, 0);
     } else {
         f = NAN;
     }
+    free(t);
+    free(u);
+    return f;
+}
+
+double orc_fitness_scale(int kind, uint32_t d, const float *x, const float *s, const float *w,
+                         const float *a)
+{
+    if (kind < ORC_F1 || kind > ORC_F9) {
+        if (kind == ORC_SPHERE) return orc_fitness(kind, d, x, s, w, a);
+        /* RIPPLE and DENSE: sums of non-negative terms */
+        return orc_fitness(kind, d, x, s, w, a);
+    }
+    double *t = (double *)malloc(sizeof(double) * (d ? d : 1));
+    double *u = (double *)malloc(sizeof(double) * (d ? d : 1));
+    const double f = paper_function(kind, d, x, t, u, 1);
     free(t);
     free(u);
     return f;

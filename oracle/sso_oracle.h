@@ -35,6 +35,21 @@ extern "C" {
 
 enum { ORC_SPHERE = 0, ORC_RIPPLE = 1, ORC_DENSE = 2 };
 
+/* The benchmark functions of Table 3.2 (unshifted), P = d variables:
+ *   F1 sphere         sum x_i^2
+ *   F2 hyper-ellipsoid sum i x_i^2                       (i from 1)
+ *   F3 Schwefel 1.2   sum_i (sum_{j<=i} x_j)^2
+ *   F4 Rosenbrock     sum_{i<P} 100 (x_{i+1} - x_i^2)^2 + (1 - x_i)^2
+ *   F5 Rastrigin      10 P + sum x_i^2 - 10 cos(2 pi x_i)
+ *   F6 Ackley         -20 exp(-0.2 sqrt(sum x_i^2 / P)) - exp(sum cos(2 pi x_i) / P) + 20 + e
+ *   F7 Griewank       sum x_i^2 / 4000 - prod cos(x_i / sqrt(i)) + 1
+ *   F8 Powell         sum over the floor(P/4) groups g of four:
+ *                     (x1 + 10 x2)^2 + 5 (x3 - x4)^2 + (x2 - 2 x3)^4 + 10 (x1 - x4)^4
+ *   F9 Schwefel 2.26  418.9829 P - sum x_i sin(sqrt(|x_i|))
+ * Where the printed table is garbled (F3, F5, F6, F8) these are the
+ * textbook forms the table names; s, w and a are not used. */
+enum { ORC_F1 = 11, ORC_F2, ORC_F3, ORC_F4, ORC_F5, ORC_F6, ORC_F7, ORC_F8, ORC_F9 };
+
 /* Source of a variable in Eq. (2.1). */
 enum { ORC_SRC_GBEST = 0, ORC_SRC_PBEST = 1, ORC_SRC_SELF = 2, ORC_SRC_FRESH = 3 };
 
@@ -72,6 +87,13 @@ float orc_fresh_value(const orc_rule *r, uint32_t word);
  * w is d (RIPPLE only). */
 double orc_fitness(int kind, uint32_t d, const float *x, const float *s, const float *w,
                    const float *a);
+
+/* Magnitude of the quantities the objective adds up at x (the same sums
+ * with every term taken by absolute value and every difference as a sum of
+ * magnitudes): the scale against which an FP32 evaluation's rounding error
+ * is bounded.  Equals f for SPHERE, F1, F2 (all terms non-negative). */
+double orc_fitness_scale(int kind, uint32_t d, const float *x, const float *s, const float *w,
+                         const float *a);
 
 /* DENSE objective at an FP64 point: f = sum_k (sum_j A_kj (x_j - s_j))^2,
  * every sum pairwise (the same sums orc_fitness forms for FP32 points). */

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "sso_oracle.c")
 PINS = ["tests/test_oracle_philox.py", "tests/test_oracle_rule.py",
         "tests/test_oracle_objectives.py", "tests/test_oracle_swarm.py",
-        "tests/test_oracle_gradient.py"]
+        "tests/test_oracle_gradient.py", "tests/test_oracle_paper.py"]
 
 MUTANTS = {
     "philox multipliers swapped": (
@@ -51,6 +51,23 @@ MUTANTS = {
     "polish gradient frozen at the first point": (
         "            for (uint32_t j = 0; j < d; ++j) p[j] = (double)q[j];\n            orc_dense_grad(d, p, sw->s, sw->a, g);",
         "            if (k == 0) {\n                for (uint32_t j = 0; j < d; ++j) p[j] = (double)q[j];\n                orc_dense_grad(d, p, sw->s, sw->a, g);\n            }"),
+    "ellipsoid weights from zero": ("t[i] = (double)(i + 1) * x[i] * x[i];",
+                                    "t[i] = (double)i * x[i] * x[i];"),
+    "Schwefel 1.2 without running sums": ("run += scale ? fabs((double)x[i]) : (double)x[i];",
+                                          "run = scale ? fabs((double)x[i]) : (double)x[i];"),
+    "Rosenbrock pair reversed": ("const double q = scale ? fabs(xn) + xi * xi : xn - xi * xi;",
+                                 "const double q = scale ? fabs(xn) + xi * xi : xi - xn * xn;"),
+    "Rastrigin without 10 P": ("f = 10.0 * P + pairwise(t, d);", "f = pairwise(t, d);"),
+    "Ackley without e": ("f = scale ? 20.0 * e_a + e_b + 20.0 + e1 : -20.0 * e_a - e_b + 20.0 + e1;",
+                         "f = scale ? 20.0 * e_a + e_b + 20.0 + e1 : -20.0 * e_a - e_b + 20.0;"),
+    "Griewank index from two": ("prod *= cos((double)x[i] / sqrt((double)(i + 1)));",
+                                "prod *= cos((double)x[i] / sqrt((double)(i + 2)));"),
+    "Powell groups overlap": (
+        "const double x1 = x[4 * k], x2 = x[4 * k + 1], x3 = x[4 * k + 2], x4 = x[4 * k + 3];",
+        "const double x1 = x[k], x2 = x[k + 1], x3 = x[k + 2], x4 = x[k + 3];"),
+    "Schwefel 2.26 sign flipped": (
+        "f = scale ? 418.9829 * P + pairwise(t, d) : 418.9829 * P - pairwise(t, d);",
+        "f = scale ? 418.9829 * P + pairwise(t, d) : 418.9829 * P + pairwise(t, d);"),
     "pBest replaced on ties": ("if (less_f32(f32, sw->fp[i])) {", "if (!less_f32(sw->fp[i], f32)) {"),
     "gBest ties to the highest index": ("if (less_f32(fp[i], fp[best])) best = i;",
                                         "if (!less_f32(fp[best], fp[i])) best = i;"),
