@@ -42,11 +42,28 @@ extern "C" {
 #define SSO_E_UNSUPPORTED -4 /* size beyond a kernel limit, or not a gfx950 GPU */
 #define SSO_E_STATE       -5 /* call out of order (e.g. trace already dropped)  */
 
-/* Objectives (all minimised; optimum 0 at x = s). */
+/* Objectives (all minimised).  SPHERE, RIPPLE and DENSE are shifted (optimum
+ * 0 at x = s).  F1..F9 are the benchmark functions of Table 3.2, unshifted,
+ * with P = d (s, w, a not used; the caller sets the box, e.g. the table's
+ * feasible bounds); where the printed table is garbled the textbook form is
+ * taken: F3 squares the running sums, F5 has the cosine, F6 has a = 20,
+ * b = 0.2, c = 2 pi and + a + e, F8 sums Powell's four terms over the
+ * floor(d/4) groups of four, F9 is meant for the box [-500, 500].  F1..F9
+ * run on the STREAM engine with d <= 1024; they are not available to
+ * batches or the RESIDENT engine. */
 typedef enum {
     SSO_OBJ_SPHERE = 0, /* sum_j (x_j - s_j)^2                                  */
     SSO_OBJ_RIPPLE = 1, /* sum_j w_j (x_j - s_j)^2 + 0.5 sum_j sin^2(3(x_j - s_j)) */
-    SSO_OBJ_DENSE  = 2  /* || A (x - s) ||^2, A is d x d                        */
+    SSO_OBJ_DENSE  = 2, /* || A (x - s) ||^2, A is d x d                        */
+    SSO_OBJ_F1_SPHERE = 11,     /* sum x_j^2                                      */
+    SSO_OBJ_F2_ELLIPSOID = 12,  /* sum j x_j^2 (j from 1)                         */
+    SSO_OBJ_F3_SCHWEFEL12 = 13, /* sum_i (sum_{j<=i} x_j)^2                       */
+    SSO_OBJ_F4_ROSENBROCK = 14, /* sum_{j<d} 100 (x_{j+1} - x_j^2)^2 + (1 - x_j)^2 */
+    SSO_OBJ_F5_RASTRIGIN = 15,  /* 10 d + sum x_j^2 - 10 cos(2 pi x_j)            */
+    SSO_OBJ_F6_ACKLEY = 16,     /* -20 e^{-0.2 sqrt(mean x^2)} - e^{mean cos 2 pi x} + 20 + e */
+    SSO_OBJ_F7_GRIEWANK = 17,   /* sum x_j^2 / 4000 - prod cos(x_j / sqrt j) + 1  */
+    SSO_OBJ_F8_POWELL = 18,     /* sum over groups of (x1+10x2)^2 + 5(x3-x4)^2 + (x2-2x3)^4 + 10(x1-x4)^4 */
+    SSO_OBJ_F9_SCHWEFEL226 = 19 /* 418.9829 d - sum x_j sin(sqrt|x_j|)            */
 } sso_objective;
 
 /* Order of the four intervals of Eq. (2.1).  A uniform word k in [0, 2^32)
@@ -96,7 +113,7 @@ typedef struct {
                             power of two in [8, 64]                               */
     uint32_t trace_cap;  /* generations of (fG, gidx, improved) kept on device;
                             0 = 4096, else >= 4                                   */
-    const float *s;      /* host [d]: shift (optimum)                             */
+    const float *s;      /* host [d]: shift (optimum); may be NULL for F1..F9      */
     const float *w;      /* host [d]: RIPPLE weights, else ignored (may be NULL)  */
     const float *a;      /* host [d*d] row-major: DENSE matrix, else ignored      */
     uint32_t polish_every; /* DENSE only: 0 = off; else after every generation t

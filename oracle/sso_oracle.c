@@ -346,10 +346,11 @@ orc_swarm *orc_create(uint32_t n, uint32_t d, int kind, float lo, float hi, doub
                       double cp, double cw, int order, uint64_t seed, uint32_t swarm,
                       const float *s, const float *w, const float *a)
 {
-    if (n == 0 || d == 0 || !s) return NULL;
+    const int paper = kind >= ORC_F1 && kind <= ORC_F9;
+    if (n == 0 || d == 0 || (!s && !paper)) return NULL;
     if (kind == ORC_RIPPLE && !w) return NULL;
     if (kind == ORC_DENSE && !a) return NULL;
-    if (kind != ORC_SPHERE && kind != ORC_RIPPLE && kind != ORC_DENSE) return NULL;
+    if (kind != ORC_SPHERE && kind != ORC_RIPPLE && kind != ORC_DENSE && !paper) return NULL;
     orc_swarm *sw = (orc_swarm *)calloc(1, sizeof *sw);
     if (orc_rule_make(cg, cp, cw, order, lo, hi, &sw->rule) != 0) {
         free(sw);

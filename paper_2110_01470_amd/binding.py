@@ -15,7 +15,8 @@ import numpy as np
 from .build import LIB_PATH
 
 OK, E_INVAL, E_NOMEM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5
-OBJ = {"sphere": 0, "ripple": 1, "dense": 2}
+OBJ = {"sphere": 0, "ripple": 1, "dense": 2, "f1": 11, "f2": 12, "f3": 13, "f4": 14, "f5": 15,
+       "f6": 16, "f7": 17, "f8": 18, "f9": 19}
 ORDER_GPS, ORDER_EQ21 = 0, 1
 ENGINE = {"auto": 0, "stream": 1, "resident": 2}
 STORAGE = {"auto": 0, "f32": 1, "u24": 2}

@@ -112,14 +112,19 @@ int validate(const sso_config *c, std::string *why)
     if (c->n == 0 || c->n >= (1u << 31)) return bad(SSO_E_INVAL, "n must be in [1, 2^31)");
     if (c->d == 0) return bad(SSO_E_INVAL, "d must be >= 1");
     if (c->d > kMaxD) return bad(SSO_E_UNSUPPORTED, "d exceeds 2^20");
-    if (c->kind < SSO_OBJ_SPHERE || c->kind > SSO_OBJ_DENSE) return bad(SSO_E_INVAL, "unknown objective kind");
+    const bool paper = is_paper_kind(c->kind);
+    if ((c->kind < SSO_OBJ_SPHERE || c->kind > SSO_OBJ_DENSE) && !paper)
+        return bad(SSO_E_INVAL, "unknown objective kind");
+    if (paper && c->d > 1024) return bad(SSO_E_UNSUPPORTED, "the Table 3.2 functions support d <= 1024");
+    if (paper && c->engine == SSO_ENGINE_RESIDENT)
+        return bad(SSO_E_UNSUPPORTED, "the Table 3.2 functions run on the STREAM engine");
     if (c->kind == SSO_OBJ_DENSE && c->d > kDenseMaxD) return bad(SSO_E_UNSUPPORTED, "dense objective supports d <= 256");
     if (c->order != SSO_ORDER_GPS && c->order != SSO_ORDER_EQ21) return bad(SSO_E_INVAL, "unknown interval order");
     if (c->engine < SSO_ENGINE_AUTO || c->engine > SSO_ENGINE_RESIDENT) return bad(SSO_E_INVAL, "unknown engine");
     if (c->lanes != 0 && (c->lanes < 8 || c->lanes > 64 || (c->lanes & (c->lanes - 1))))
         return bad(SSO_E_INVAL, "lanes must be 0 or a power of two in [8, 64]");
     if (c->trace_cap != 0 && c->trace_cap < 4) return bad(SSO_E_INVAL, "trace_cap must be 0 or >= 4");
-    if (!c->s) return bad(SSO_E_INVAL, "s is NULL");
+    if (!c->s && !paper) return bad(SSO_E_INVAL, "s is NULL");
     if (c->kind == SSO_OBJ_RIPPLE && !c->w) return bad(SSO_E_INVAL, "ripple objective needs w");
     if (c->kind == SSO_OBJ_DENSE && !c->a) return bad(SSO_E_INVAL, "dense objective needs a");
     if (!std::isfinite(c->lo) || !std::isfinite(c->hi) || !(c->lo < c->hi))
@@ -180,7 +185,7 @@ void set_params(const sso_config &c, SwarmDev &S)
 int upload_separable(const sso_config &c, const SwarmDev &S, hipStream_t st, std::string *err)
 {
     std::vector<float> pad(S.dp, 0.0f);
-    std::memcpy(pad.data(), c.s, sizeof(float) * c.d);
+    if (c.s) std::memcpy(pad.data(), c.s, sizeof(float) * c.d);  // Table 3.2's functions have none
     HIP_TRY(err, hipMemcpyAsync((void *)S.s, pad.data(), sizeof(float) * S.dp, hipMemcpyHostToDevice, st));
     HIP_TRY(err, hipStreamSynchronize(st));
     if (c.kind == SSO_OBJ_RIPPLE) {

@@ -213,6 +213,142 @@ __device__ __forceinline__ float terms4_full(f4 x, f4 s, f4 w)
 }
 
 // ---------------------------------------------------------------------------
+// Table 3.2's benchmark functions, unshifted, over the d variables of a
+// particle (F3, F5, F6 and F8 in the textbook forms the garbled entries name:
+// the running sums of Schwefel 1.2, Rastrigin's cosine, Ackley with
+// a = 20, b = 0.2, c = 2 pi and + a + e, Powell's four terms per group of
+// four).  A particle's L lanes accumulate their chunks into PaperAcc; F3 needs
+// running sums across the lanes (a scan of chunk totals plus a carry from
+// the previous pass) and F4 the last variable of the previous chunk (the
+// lane below, or for lane 0 the carry from the previous pass).  All lanes of
+// a particle call paper_chunk together for the chunks c = c0 + ln of one
+// pass; a lane whose chunk does not exist has left the loop, and its values
+// are never needed.
+// ---------------------------------------------------------------------------
+struct PaperAcc {
+    float a = 0.0f, b = 0.0f, p = 1.0f, carry = 0.0f;
+};
+
+__device__ __forceinline__ float rosen_pair(float xi, float xn)
+{
+    const float q = xn - xi * xi, r = 1.0f - xi;
+    return 100.0f * (q * q) + r * r;
+}
+
+__device__ __forceinline__ void paper_chunk(PaperAcc &q, f4 x, uint32_t c, uint32_t d, uint32_t L,
+                                            uint32_t ln, int kind)
+{
+    const uint32_t j0 = 4u * c;
+    const float v[4] = {x.x, x.y, x.z, x.w};
+    switch (kind) {
+    case OBJ_F1 + 0:  // sphere
+#pragma unroll
+        for (uint32_t e = 0; e < 4; ++e)
+            if (j0 + e < d) q.a += v[e] * v[e];
+        break;
+    case OBJ_F1 + 1:  // hyper-ellipsoid: the square of variable j weighs j + 1
+#pragma unroll
+        for (uint32_t e = 0; e < 4; ++e)
+            if (j0 + e < d) q.a += (float)(j0 + e + 1) * (v[e] * v[e]);
+        break;
+    case OBJ_F1 + 2: {  // Schwefel 1.2: squares of the running sums
+        float pre[4], r = 0.0f;
+#pragma unroll
+        for (uint32_t e = 0; e < 4; ++e) {
+            r += (j0 + e < d) ? v[e] : 0.0f;
+            pre[e] = r;
+        }
+        float incl = r;  // inclusive scan of the chunk totals over the lanes
+        for (uint32_t off = 1; off < L; off <<= 1) {
+            const float u = __shfl_up(incl, off, L);
+            if (ln >= off) incl += u;
+        }
+        // Shuffles run in every lane before any select: a lane whose
+        // execution bit is off does not supply its value to a permute, so a
+        // shuffle inside the ln != 0 branch would read nothing from lane 0.
+        const float up1 = __shfl_up(incl, 1, L);
+        const float excl = ln ? up1 : 0.0f;
+        const float base = q.carry + excl;
+#pragma unroll
+        for (uint32_t e = 0; e < 4; ++e)
+            if (j0 + e < d) {
+                const float run = base + pre[e];
+                q.a += run * run;
+            }
+        q.carry += __shfl(incl, L - 1, L);
+        break;
+    }
+    case OBJ_F1 + 3: {  // Rosenbrock: pairs (x_j, x_{j+1})
+#pragma unroll
+        for (uint32_t e = 0; e < 3; ++e)
+            if (j0 + e + 1 < d) q.a += rosen_pair(v[e], v[e + 1]);
+        // The pair that straddles chunks c-1 and c belongs to chunk c.
+        const float below = __shfl_up(v[3], 1, L);
+        const float prev = ln ? below : q.carry;
+        if (c > 0 && j0 < d) q.a += rosen_pair(prev, v[0]);
+        q.carry = __shfl(v[3], L - 1, L);
+        break;
+    }
+    case OBJ_F1 + 4:  // Rastrigin (10 d is added at the end)
+#pragma unroll
+        for (uint32_t e = 0; e < 4; ++e)
+            if (j0 + e < d) q.a += v[e] * v[e] - 10.0f * cospif(2.0f * v[e]);
+        break;
+    case OBJ_F1 + 5:  // Ackley: sum of squares, sum of cos(2 pi x)
+#pragma unroll
+        for (uint32_t e = 0; e < 4; ++e)
+            if (j0 + e < d) {
+                q.a += v[e] * v[e];
+                q.b += cospif(2.0f * v[e]);
+            }
+        break;
+    case OBJ_F1 + 6:  // Griewank: sum of squares, product of cos(x_j / sqrt(j + 1))
+#pragma unroll
+        for (uint32_t e = 0; e < 4; ++e)
+            if (j0 + e < d) {
+                q.a += v[e] * v[e];
+                q.p *= cosf(v[e] / sqrtf((float)(j0 + e + 1)));
+            }
+        break;
+    case OBJ_F1 + 7:  // Powell: chunk c is group c; only whole groups count
+        if (j0 + 3 < d) {
+            const float a1 = v[0] + 10.0f * v[1], a2 = v[2] - v[3];
+            const float a3 = v[1] - 2.0f * v[2], a4 = v[0] - v[3];
+            const float a3s = a3 * a3, a4s = a4 * a4;
+            q.a += a1 * a1 + 5.0f * (a2 * a2) + a3s * a3s + 10.0f * (a4s * a4s);
+        }
+        break;
+    default:  // F9, Schwefel 2.26: 418.9829 d is added at the end
+#pragma unroll
+        for (uint32_t e = 0; e < 4; ++e)
+            if (j0 + e < d) q.a += v[e] * sinf(sqrtf(fabsf(v[e])));
+        break;
+    }
+}
+
+// The particle's value from its lanes' accumulators (a butterfly over the
+// L lanes, then the function's outer terms).
+__device__ __forceinline__ float paper_finish(PaperAcc q, uint32_t L, uint32_t d, int kind)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        if ((uint32_t)m < L) {
+            q.a += __shfl_xor(q.a, m, 64);
+            q.b += __shfl_xor(q.b, m, 64);
+            q.p *= __shfl_xor(q.p, m, 64);
+        }
+    const float P = (float)d;
+    switch (kind) {
+    case OBJ_F1 + 4: return 10.0f * P + q.a;
+    case OBJ_F1 + 5:
+        return -20.0f * expf(-0.2f * sqrtf(q.a / P)) - expf(q.b / P) + 20.0f + 2.718281828459045f;
+    case OBJ_F1 + 6: return q.a / 4000.0f - q.p + 1.0f;
+    case OBJ_F1 + 8: return 418.9829f * P - q.a;
+    default: return q.a;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // gBest key: (orderable FP32 bits << 32) | (particle << 1) | pBest row.
 // Smaller fitness wins; equal fitness goes to the lower particle index; NaN
 // sorts above every number; -0 and +0 are the same.

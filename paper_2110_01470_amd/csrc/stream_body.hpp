@@ -29,11 +29,15 @@ constexpr uint32_t chunk_words() { return sizeof(typename Store::T) == 16 && !St
 // Dynamic LDS of the staged kernels: shift, ripple weights, gBest row.
 constexpr uint32_t kStageMaxChunks = 256;  // d <= 1024
 
+// Shift and weight arrays staged in LDS: ripple both, sphere the shift,
+// Table 3.2's functions neither.
+template <int KIND>
+constexpr uint32_t staged_arrays() { return KIND == OBJ_RIPPLE ? 2u : KIND == OBJ_PAPER ? 0u : 1u; }
+
 template <int KIND, class Store>
 inline size_t stage_bytes(const SwarmDev &S)
 {
-    return (size_t)S.chunks * 16u * (KIND == OBJ_RIPPLE ? 2u : 1u) +
-           (size_t)S.chunks * chunk_words<Store>() * 4u;
+    return (size_t)S.chunks * 16u * staged_arrays<KIND>() + (size_t)S.chunks * chunk_words<Store>() * 4u;
 }
 
 // One generation t (the initialisation when INIT) for the particles of
@@ -81,12 +85,12 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
     const f4 zero = f4{0.f, 0.f, 0.f, 0.f};
     f4 *ls = lds_dyn;                                              // [chunks] shift
     f4 *lw = lds_dyn + S.chunks;                                   // [chunks] weights
-    uint32_t *lg = reinterpret_cast<uint32_t *>(lds_dyn + (KIND == OBJ_RIPPLE ? 2 : 1) * S.chunks);
+    uint32_t *lg = reinterpret_cast<uint32_t *>(lds_dyn + staged_arrays<KIND>() * S.chunks);
 
     // Loads that do not depend on gBest go out before the start-of-generation
     // barrier: the shift and weights for staging, this lane's first pBest and
     // position (as stored; unpacked when the chunk is computed).
-    if constexpr (STAGE) {
+    if constexpr (STAGE && KIND != OBJ_PAPER) {
         for (uint32_t q = tid; q < S.chunks; q += blockDim.x) {
             ls[q] = s4[q];
             if (KIND == OBJ_RIPPLE) lw[q] = w4[q];
@@ -110,6 +114,7 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
     if constexpr (STAGE) __syncthreads();
 
     float acc = 0.0f;
+    PaperAcc pacc;
     if (valid) {
         // Software pipeline: the next chunk's rows are requested before this
         // chunk is computed.
@@ -131,20 +136,28 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
                 xn = Store::template select<EQ21>(S, k, g, pc, xc);
             }
             Store::store(xrow_ptr, c, xn);
-            const f4 sv = STAGE ? ls[c] : s4[c];
-            const f4 wv = (KIND == OBJ_RIPPLE) ? (STAGE ? lw[c] : w4[c]) : zero;
             const f4 xf = Store::value(S, xn);
-            if constexpr (RAGGED)
-                acc += terms4<KIND>(xf, sv, wv, 4u * c, S.d);
-            else
-                acc += terms4_full<KIND>(xf, sv, wv);
+            if constexpr (KIND == OBJ_PAPER) {
+                paper_chunk(pacc, xf, c, S.d, L, ln, S.kind);
+            } else {
+                const f4 sv = STAGE ? ls[c] : s4[c];
+                const f4 wv = (KIND == OBJ_RIPPLE) ? (STAGE ? lw[c] : w4[c]) : zero;
+                if constexpr (RAGGED)
+                    acc += terms4<KIND>(xf, sv, wv, 4u * c, S.d);
+                else
+                    acc += terms4_full<KIND>(xf, sv, wv);
+            }
         }
     }
     // Butterfly over the L lanes of the particle (the masks are immediates;
     // with a runtime width the steps above it are skipped uniformly).
+    if constexpr (KIND == OBJ_PAPER) {
+        acc = paper_finish(pacc, L, S.d, S.kind);
+    } else {
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1)
-        if ((uint32_t)m < L) acc += __shfl_xor(acc, m, 64);
+        for (int m = 32; m >= 1; m >>= 1)
+            if ((uint32_t)m < L) acc += __shfl_xor(acc, m, 64);
+    }
 
     // Algorithm 3: replace the pBest on a strict improvement (NaN never does).
     const bool improved = valid && (INIT || acc < fpi);

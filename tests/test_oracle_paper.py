@@ -124,3 +124,20 @@ def test_scale_bounds_the_value(kind):
         assert sc >= abs(v) - 1e-9 * sc
         if kind in (oracle.F1, oracle.F2):
             assert sc == v
+
+
+@pytest.mark.parametrize("kind", range(oracle.F1, oracle.F9 + 1))
+def test_swarm_runs_on_each_function(kind):
+    """A swarm on each function (no shift arrays): the pBest fitness never
+    increases, it is the function's value at the pBest, and gBest is the
+    lowest-index argmin."""
+    sw = oracle.Swarm(30, 13, kind, -2.0, 2.0, 0.8, 0.6, 0.3, 1001, None, order=oracle.ORDER_EQ21)
+    sw.init()
+    prev = sw.fp.copy()
+    for _ in range(15):
+        sw.step()
+        assert np.all(sw.fp <= prev)
+        prev = sw.fp.copy()
+    for i in range(30):
+        assert sw.fp64[i] == oracle.fitness(kind, sw.p[i], None)
+    assert sw.gidx == oracle.argmin(sw.fp)
