@@ -170,14 +170,16 @@ def copy_calibration(nbytes, reps=5):
 
 
 def main():
-    from paper_2110_01470_amd.inputs import BATCH_WORKLOADS, WORKLOADS
+    from paper_2110_01470_amd.inputs import BATCH_WORKLOADS, PAPER_WORKLOADS, WORKLOADS
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed generations (default: the workload's)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ripple_n65536_d1000",
-                    choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS))
+                    choices=sorted(WORKLOADS) + sorted(BATCH_WORKLOADS) + sorted(PAPER_WORKLOADS))
+    ap.add_argument("--paper-quality", action="store_true",
+                    help="final gBest of f1..f9 at the paper's settings over seeds 1001..1020")
     ap.add_argument("--polish", action="store_true",
                     help="dense workload: time-to-gap of plain SSO vs SSO with a gradient "
                          "polish of all pBests every 50 generations")
@@ -200,8 +202,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.paper_quality:
+        paper_quality(PAPER_WORKLOADS, args)
+        return
     if args.workload in BATCH_WORKLOADS:
         bench_batch(BATCH_WORKLOADS[args.workload], args)
+        return
+    if args.workload in PAPER_WORKLOADS:
+        bench_paper(PAPER_WORKLOADS[args.workload], args)
         return
 
     wl = WORKLOADS[args.workload]
@@ -263,6 +271,128 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
+
+
+# The paper's PSSO wall times (GTX 1080) for its Rosenbrock runs, Table 3.10:
+# P = 50, 1000 iterations, (Cw, Cp, Cg) = (0.3, 0.6, 0.8).
+PAPER_F4_SECONDS = {100: 0.13875, 200: 0.154, 300: 0.1638, 350: 0.1695}
+# The paper's PSSO solution quality at D = 50, N = 100, T = 1000 over 20 runs
+# (average, standard deviation, minimum), for the functions it lists legibly.
+PAPER_QUALITY = {"f1": (41.0156, 5.3095, 28.5125), "f4": (1103.9103, 134.5448, 730.0332),
+                 "f5": (220.6183, 16.2710, 189.2935)}
+
+
+def paper_swarm(pw, seed=None, stream=None):
+    from paper_2110_01470_amd.binding import Swarm
+
+    return Swarm(pw.n, pw.d, pw.kind, pw.lo, pw.hi, pw.cg, pw.cp, pw.cw,
+                 pw.seed if seed is None else seed, None, order=1, engine="stream",
+                 stream=stream)
+
+
+def bench_paper(pw, args):
+    """A Table 3.2 function at the paper's settings.  The paper times whole
+    runs (set-up, T iterations, result back on the host), so the line's value
+    is that wall time, measured on the host clock: swarm creation (upload and
+    initialisation), the T generations, and the gBest copy back."""
+    import torch
+
+    from paper_2110_01470_amd.binding import Swarm  # noqa: F401  (loads the library)
+
+    steps = args.steps if args.steps is not None else pw.generations
+    stream = torch.cuda.Stream()
+    for _ in range(max(1, args.warmup // 10)):  # warm-up whole runs
+        sw = paper_swarm(pw, stream=stream)
+        sw.run(steps)
+        sw.best()
+        sw.close()
+    walls = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sw = paper_swarm(pw, stream=stream)
+        sw.run(steps)
+        g, fg, gidx, gen = sw.best()
+        walls.append(time.perf_counter() - t0)
+        sw.close()
+    wall = float(np.median(walls))
+    # The generations alone, with HIP events.
+    sw = paper_swarm(pw, stream=stream)
+    stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sw.run(steps)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / steps
+    updates = pw.n * pw.d * steps
+    log(f"{pw.name}: whole run {wall * 1e3:.2f} ms (median of 5), generations {ms:.2f} ms, "
+        f"final fG {fg:.6g}")
+    byt = BYTES_PER_UPDATE * pw.n * pw.d
+    achieved = byt / (ms_per_step / 1e3) / 1e9
+    paper_s = PAPER_F4_SECONDS.get(pw.n) if pw.kind == "f4" and pw.d == 50 else None
+    cpu = None
+    if args.cpu_gens is None or args.cpu_gens > 0:
+        import oracle
+
+        orc = oracle.Swarm(pw.n, pw.d, oracle.F1 + int(pw.kind[1:]) - 1, pw.lo, pw.hi, pw.cg, pw.cp,
+                           pw.cw, pw.seed, None, order=oracle.ORDER_EQ21)
+        t0 = time.perf_counter()
+        orc.init()
+        orc.run(steps)
+        csec = time.perf_counter() - t0
+        cpu = {"value": csec, "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole {steps}-generation run of {pw.name}, single-threaded FP64 oracle"}
+    rec = {
+        "metric": "wall time of a whole run (set-up, T generations, gBest to host)",
+        "value": wall,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": max(1, args.warmup // 10),
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": wall / paper_s if paper_s else None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": pw.name, "objective": pw.kind, "n": pw.n, "d": pw.d,
+                   "generations": steps, "box": [pw.lo, pw.hi], "order": "eq21",
+                   "cw_cp_cg": [pw.cw, pw.cp, pw.cg]},
+        "updates_per_s": updates / (ms / 1e3),
+        "final_fG": fg,
+        "paper_context": ({"seconds": paper_s, "hardware": "GTX 1080", "source": "Table 3.10"}
+                          if paper_s else None),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def paper_quality(workloads, args):
+    """Final gBest fitness of each Table 3.2 function at the paper's settings
+    (D = 50, N = 100, T = 1000, (Cw, Cp, Cg) = (0.3, 0.6, 0.8)) over the 20
+    replicate seeds, beside the paper's own PSSO figures where legible."""
+    import torch
+
+    stream = torch.cuda.Stream()
+    out = {}
+    for k in range(1, 10):
+        pw = workloads[f"paper_f{k}_n100_d50"]
+        finals = []
+        for seed in range(1001, 1021):
+            sw = paper_swarm(pw, seed=seed, stream=stream)
+            sw.run(pw.generations)
+            finals.append(sw.best()[1])
+            sw.close()
+        v = np.array(finals, np.float64)
+        out[pw.kind] = {"mean": float(v.mean()), "std": float(v.std(ddof=1)), "min": float(v.min()),
+                        "paper": PAPER_QUALITY.get(pw.kind)}
+        log(f"{pw.kind}: {v.mean():.4f} +- {v.std(ddof=1):.4f} (min {v.min():.4f})")
+    print(json.dumps({"paper_quality": out, "runs": 20, "d": 50, "n": 100, "generations": 1000}),
+          flush=True)
 
 
 POLISH_EVERY, POLISH_STEPS = 50, 5
