@@ -23,18 +23,17 @@
 //   * the A operands are one float4 per lane and row block; the host packs A
 //     as [M][row block][lane][4] so that K-chunk M is one contiguous block
 //     that the workgroup copies into LDS and each wave reads conflict-free.
-// The two K-chunks of a step (one per half) are double-buffered in LDS; the
-// next step's global loads and the next select's row loads are issued
-// before the current step's MFMAs.
+// The two K-chunks of a step (one per half) are double-buffered in LDS and
+// copied there by global-to-LDS loads (no registers in between); the next
+// step's copy and the next select's row loads are issued before the current
+// step's MFMAs, which read their A operands from LDS four row blocks at a
+// time.
 #include "sso_device.hpp"
 
 namespace sso {
 
 typedef f4 floatx4;
 
-#ifndef SSO_DENSE_DIRECT_A
-#define SSO_DENSE_DIRECT_A 0
-#endif
 constexpr int kDenseWaves = 8;
 constexpr int kDenseBlock = 64 * kDenseWaves;
 
@@ -103,23 +102,21 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     auto stage_addr = [&](uint32_t m, uint32_t q) -> size_t {
         return (size_t)(q < CF4 ? m : HALF + m) * CF4 + (q % CF4);
     };
+    // Step m's two K-chunks straight from global memory into LDS buffer b:
+    // each wave moves 64 consecutive float4 (no registers in between).
+    auto stage_dma = [&](uint32_t m, uint32_t b) {
+#pragma unroll
+        for (uint32_t r = 0; r < PER; ++r) {
+            const uint32_t q = tid + r * kDenseBlock;
+            if (FULL || q < STEP_F4)
+                __builtin_amdgcn_global_load_lds(
+                    (const void *)(a_pack + stage_addr(m, q)),
+                    (__attribute__((address_space(3))) void *)(&lds[b][r * kDenseBlock + wave * 64u]), 16, 0, 0);
+        }
+    };
     // Loads that do not depend on gBest go out before the start-of-generation
     // barrier: the first A step and this lane's first pBest, position, shift.
-    f4 stage0[PER];
-#if SSO_DENSE_DIRECT_A
-    // Each wave reads its own A operands straight from global memory (A is
-    // L2-resident), one step ahead; no staging and no barrier in the loop.
-    const uint32_t mbase = HALF * half;  // this wave's first K-chunk
-    f4 av[NB];
-#pragma unroll
-    for (uint32_t rb = 0; rb < NB; ++rb) av[rb] = a_pack[(size_t)mbase * CF4 + rb * 64u + lane];
-#else
-#pragma unroll
-    for (uint32_t r = 0; r < PER; ++r) {
-        const uint32_t q = tid + r * kDenseBlock;
-        if (FULL || q < STEP_F4) stage0[r] = a_pack[stage_addr(0, q)];
-    }
-#endif
+    stage_dma(0, 0);
     const uint32_t cbase = 4u * HALF * half;  // first chunk of this wave's half
     const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
     f4 pv = zero4, xv = zero4, gv = zero4, sv = zero4;
@@ -148,13 +145,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
             }
         }
     };
-#if !SSO_DENSE_DIRECT_A
-#pragma unroll
-    for (uint32_t r = 0; r < PER; ++r) {
-        const uint32_t q = tid + r * kDenseBlock;
-        if (FULL || q < STEP_F4) lds[0][q] = stage0[r];
-    }
-#endif
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's DMA into buffer 0 has landed
 
     f4 acc[NB];
 #pragma unroll
@@ -186,63 +177,27 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
             dv.z = (j0 + 2 < S.d) ? xn.z - sv.z : 0.f;
             dv.w = (j0 + 3 < S.d) ? xn.w - sv.w : 0.f;
         }
-#if SSO_DENSE_DIRECT_A
-        f4 avn[NB];
         if (more) {
             prefetch(c + 4u);
-#pragma unroll
-            for (uint32_t rb = 0; rb < NB; ++rb)
-                avn[rb] = a_pack[(size_t)(mbase + m + 1) * CF4 + rb * 64u + lane];
-        }
-#else
-        f4 stage[PER];
-        if (more) {
-            prefetch(c + 4u);
-#pragma unroll
-            for (uint32_t r = 0; r < PER; ++r) {
-                const uint32_t q = tid + r * kDenseBlock;
-                if (FULL || q < STEP_F4) stage[r] = a_pack[stage_addr(m + 1, q)];
-            }
+            stage_dma(m + 1, cur ^ 1u);
         }
         const f4 *la = lds[cur] + half * CF4;
-        f4 av[NB];
 #pragma unroll
-        for (uint32_t rb = 0; rb < NB; ++rb) av[rb] = la[rb * 64u + lane];
-#endif
-        // Y^T += A[:, chunk] * D^T[chunk, :] for every row block; the
-        // e-outer order keeps consecutive MFMAs on different accumulators.
+        for (uint32_t r0 = 0; r0 < NB; r0 += 4) {
+            f4 a4[4];
 #pragma unroll
-        for (uint32_t rb = 0; rb < NB; ++rb)
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb][0], dv.x, acc[rb], 0, 0, 0);
+            for (uint32_t q = 0; q < 4 && r0 + q < NB; ++q) a4[q] = la[(r0 + q) * 64u + lane];
 #pragma unroll
-        for (uint32_t rb = 0; rb < NB; ++rb)
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb][1], dv.y, acc[rb], 0, 0, 0);
+            for (uint32_t e = 0; e < 4; ++e)
 #pragma unroll
-        for (uint32_t rb = 0; rb < NB; ++rb)
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb][2], dv.z, acc[rb], 0, 0, 0);
-#pragma unroll
-        for (uint32_t rb = 0; rb < NB; ++rb)
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb][3], dv.w, acc[rb], 0, 0, 0);
-#if SSO_DENSE_DIRECT_A
-        if (more) {
-#pragma unroll
-            for (uint32_t rb = 0; rb < NB; ++rb) av[rb] = avn[rb];
+                for (uint32_t q = 0; q < 4 && r0 + q < NB; ++q)
+                    acc[r0 + q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[q][e], dv[e], acc[r0 + q], 0, 0, 0);
         }
-        (void)cur;
-#else
         if (more) {
-#pragma unroll
-            for (uint32_t r = 0; r < PER; ++r) {
-                const uint32_t q = tid + r * kDenseBlock;
-                if (FULL || q < STEP_F4) lds[cur ^ 1u][q] = stage[r];
-            }
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's DMA for the next step has landed
         }
         __syncthreads();
-#endif
     }
-#if SSO_DENSE_DIRECT_A
-    __syncthreads();
-#endif
 
     // The upper half hands its partial Y^T to the lower half through LDS
     // (the staging buffers are free after the loop's last barrier).
