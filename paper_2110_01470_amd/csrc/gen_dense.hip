@@ -61,7 +61,8 @@ void dense_pack_matrix(const float *a, uint32_t d, float *out)
 }
 
 // NB = dp / 16: row blocks of A, and K-chunks of 16 variables (NB is even).
-template <int NB, bool EQ21, bool INIT>
+// FULL_D: d = dp, so every chunk is whole and inside the row (no masks).
+template <int NB, bool EQ21, bool INIT, bool FULL_D>
 __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
 {
     constexpr uint32_t HALF = NB / 2;                               // K-chunks per wave
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
         if (valid && cbase + lg < S.chunks) gv = g4[cbase + lg];
     }
     auto prefetch = [&](uint32_t c) {
-        if (valid && c < S.chunks) {
+        if (valid && (FULL_D || c < S.chunks)) {
             sv = s4[c];
             if constexpr (!INIT) {
                 pv = p4[c];
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
         // Select this lane's chunk c of Eq. (2.1) and form d = x' - s.
         const uint32_t c = cbase + 4u * m + lg;
         f4 dv = zero4;
-        if (valid && c < S.chunks) {
+        if (valid && (FULL_D || c < S.chunks)) {
             const uint4 k = words4(S, c, i, t);
             f4 xn;
             if constexpr (INIT)
@@ -171,11 +172,15 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
             else
                 xn = select4<EQ21>(S, k, gv, pv, xv);
             x4[c] = xn;
-            const uint32_t j0 = 4u * c;
-            dv.x = (j0 + 0 < S.d) ? xn.x - sv.x : 0.f;
-            dv.y = (j0 + 1 < S.d) ? xn.y - sv.y : 0.f;
-            dv.z = (j0 + 2 < S.d) ? xn.z - sv.z : 0.f;
-            dv.w = (j0 + 3 < S.d) ? xn.w - sv.w : 0.f;
+            if constexpr (FULL_D) {
+                dv = xn - sv;
+            } else {
+                const uint32_t j0 = 4u * c;
+                dv.x = (j0 + 0 < S.d) ? xn.x - sv.x : 0.f;
+                dv.y = (j0 + 1 < S.d) ? xn.y - sv.y : 0.f;
+                dv.z = (j0 + 2 < S.d) ? xn.z - sv.z : 0.f;
+                dv.w = (j0 + 3 < S.d) ? xn.w - sv.w : 0.f;
+            }
         }
         if (more) {
             prefetch(c + 4u);
@@ -242,21 +247,30 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     }
 }
 
-template <int NB>
-static void launch_nb(const SwarmDev &S, uint32_t t, dim3 grid, hipStream_t st)
+template <int NB, bool FULL_D>
+static void launch_nbf(const SwarmDev &S, uint32_t t, dim3 grid, hipStream_t st)
 {
     const bool eq21 = S.order != 0;
     if (t == 0) {
         if (eq21)
-            hipLaunchKernelGGL((k_dense<NB, true, true>), grid, dim3(kDenseBlock), 0, st, S, t);
+            hipLaunchKernelGGL((k_dense<NB, true, true, FULL_D>), grid, dim3(kDenseBlock), 0, st, S, t);
         else
-            hipLaunchKernelGGL((k_dense<NB, false, true>), grid, dim3(kDenseBlock), 0, st, S, t);
+            hipLaunchKernelGGL((k_dense<NB, false, true, FULL_D>), grid, dim3(kDenseBlock), 0, st, S, t);
     } else {
         if (eq21)
-            hipLaunchKernelGGL((k_dense<NB, true, false>), grid, dim3(kDenseBlock), 0, st, S, t);
+            hipLaunchKernelGGL((k_dense<NB, true, false, FULL_D>), grid, dim3(kDenseBlock), 0, st, S, t);
         else
-            hipLaunchKernelGGL((k_dense<NB, false, false>), grid, dim3(kDenseBlock), 0, st, S, t);
+            hipLaunchKernelGGL((k_dense<NB, false, false, FULL_D>), grid, dim3(kDenseBlock), 0, st, S, t);
     }
+}
+
+template <int NB>
+static void launch_nb(const SwarmDev &S, uint32_t t, dim3 grid, hipStream_t st)
+{
+    if (S.d == S.dp)
+        launch_nbf<NB, true>(S, t, grid, st);
+    else
+        launch_nbf<NB, false>(S, t, grid, st);
 }
 
 int launch_dense_generation(const SwarmDev &S, uint32_t t, void *stream)
