@@ -70,10 +70,14 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     constexpr uint32_t STEP_F4 = 2 * CF4;                           // both halves' chunks
     constexpr uint32_t PER = (STEP_F4 + kDenseBlock - 1) / kDenseBlock;
     constexpr bool FULL = STEP_F4 % kDenseBlock == 0;
-    // Two step buffers; after the loop the same memory carries the upper
-    // halves' partial accumulators (4 groups x NB x 64 lanes x 4 floats).
-    static_assert(2 * STEP_F4 >= 4 * NB * 64, "reduction buffer fits the staging buffers");
-    __shared__ f4 lds[2][STEP_F4];
+    // Two step buffers, as two variables: the compiler then tells the LDS
+    // reads of one from the copies in flight into the other, and does not
+    // wait for those copies before the reads.  After the loop the buffers
+    // carry the upper halves' partial accumulators (groups 0-1 in the first,
+    // 2-3 in the second; NB x 64 lanes x 4 floats each).
+    static_assert(STEP_F4 == 2 * NB * 64, "a buffer holds two groups' partial accumulators");
+    __shared__ f4 lds0[STEP_F4];
+    __shared__ f4 lds1[STEP_F4];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u, wave = tid >> 6;
@@ -82,6 +86,10 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     const uint32_t i = blockIdx.x * 64u + grp4 * 16u + pcol;
     const bool valid = i < S.n;
     const f4 *a_pack = reinterpret_cast<const f4 *>(S.a);
+
+    // The gBest key load goes out first (see generation_key_load).
+    unsigned long long gkey = ~0ull;
+    if constexpr (!INIT) gkey = generation_key_load(S, t);
 
     uint32_t prow = 0;
     bool alias = true;
@@ -112,12 +120,14 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
             if (FULL || q < STEP_F4)
                 __builtin_amdgcn_global_load_lds(
                     (const void *)(a_pack + stage_addr(m, q)),
-                    (__attribute__((address_space(3))) void *)(&lds[b][r * kDenseBlock + wave * 64u]), 16, 0, 0);
+                    (__attribute__((address_space(3))) void *)(&(b ? lds1 : lds0)[r * kDenseBlock + wave * 64u]), 16, 0, 0);
         }
     };
     // Loads that do not depend on gBest go out before the start-of-generation
-    // barrier: the first A step and this lane's first pBest, position, shift.
-    stage_dma(0, 0);
+    // barrier: this lane's first pBest, position and shift.  The first A step
+    // follows the gBest reduction (at generation 0 there is none): copies into
+    // LDS still in flight would hold up its shuffles and barrier.
+    if constexpr (INIT) stage_dma(0, 0);
     const uint32_t cbase = 4u * HALF * half;  // first chunk of this wave's half
     const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
     f4 pv = zero4, xv = zero4, gv = zero4, sv = zero4;
@@ -129,11 +139,17 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
         }
     }
 
+    // The first step's random words while those loads are in flight (the
+    // empty asm keeps them from being computed after the waits below).
+    uint4 k_first = words4(S, cbase + lg, i, t);
+    asm volatile("" : "+v"(k_first.x), "+v"(k_first.y), "+v"(k_first.z), "+v"(k_first.w));
+
     const f4 *g4 = reinterpret_cast<const f4 *>(S.rows);
     if constexpr (!INIT) {
-        const uint32_t glow = (uint32_t)generation_begin(S, t, blockIdx.x);
+        const uint32_t glow = (uint32_t)generation_begin(S, t, blockIdx.x, gkey);
         const uint32_t gidx = min(glow >> 1, S.n - 1u);
         g4 = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.stride);
+        stage_dma(0, 0);
         if (valid && cbase + lg < S.chunks) gv = g4[cbase + lg];
     }
     auto prefetch = [&](uint32_t c) {
@@ -165,7 +181,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
         const uint32_t c = cbase + 4u * m + lg;
         f4 dv = zero4;
         if (valid && (FULL_D || c < S.chunks)) {
-            const uint4 k = words4(S, c, i, t);
+            const uint4 k = m == 0 ? k_first : words4(S, c, i, t);
             f4 xn;
             if constexpr (INIT)
                 xn = init4(S, k);
@@ -186,7 +202,10 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
             prefetch(c + 4u);
             stage_dma(m + 1, cur ^ 1u);
         }
-        const f4 *la = lds[cur] + half * CF4;
+        // Keep the copies and loads above ahead of the MFMAs below, so that
+        // their latency runs under the MFMAs rather than before the barrier.
+        __builtin_amdgcn_sched_barrier(0);
+        const f4 *la = (cur ? lds1 : lds0) + half * CF4;
 #pragma unroll
         for (uint32_t r0 = 0; r0 < NB; r0 += 4) {
             f4 a4[4];
@@ -206,10 +225,10 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
 
     // The upper half hands its partial Y^T to the lower half through LDS
     // (the staging buffers are free after the loop's last barrier).
-    f4 *red = &lds[0][0];
+    f4 *red = (grp4 < 2 ? lds0 : lds1) + (grp4 & 1u) * NB * 64u;
     if (half == 1) {
 #pragma unroll
-        for (uint32_t rb = 0; rb < NB; ++rb) red[(grp4 * NB + rb) * 64u + lane] = acc[rb];
+        for (uint32_t rb = 0; rb < NB; ++rb) red[rb * 64u + lane] = acc[rb];
     }
     __syncthreads();
 
@@ -218,7 +237,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     if (half == 0) {
 #pragma unroll
         for (uint32_t rb = 0; rb < NB; ++rb) {
-            const f4 y = acc[rb] + red[(grp4 * NB + rb) * 64u + lane];
+            const f4 y = acc[rb] + red[rb * 64u + lane];
             f += y[0] * y[0];
             f += y[1] * y[1];
             f += y[2] * y[2];

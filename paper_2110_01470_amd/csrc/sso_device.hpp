@@ -389,20 +389,32 @@ __device__ __forceinline__ uint32_t *sub_cnt(const SwarmDev &S, uint32_t group, 
     return reinterpret_cast<uint32_t *>(sub_key(S, group, j) + 1);
 }
 
+// The gBest key of generation t - 1 as lane l of wave 0 holds it before the
+// reduction: sub-slot l of group (t - 1) mod 3 (all ones for unused lanes
+// and other waves).  A separate call so that a kernel can issue this load
+// ahead of its other loads: it heads the longest dependent chain of a
+// generation (key, then gBest row, then the first select).
+__device__ __forceinline__ unsigned long long generation_key_load(const SwarmDev &S, uint32_t t)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    return (threadIdx.x < 64u && lane < S.nsub) ? *sub_key(S, (t - 1u) % kGroups, lane) : ~0ull;
+}
+
 // Start of generation t >= 1 (all threads of the workgroup call it; it holds
-// one barrier).  Wave 0 reduces the sub-slots of generation t - 1 (one load
-// per lane, nsub <= 64) and shares the gBest key through LDS.  Workgroup 0
-// of the swarm (blk == 0) also records that key and the improvement count in
-// the trace ring and clears the group generation t + 1 will commit into.
+// one barrier).  Wave 0 reduces the sub-slots of generation t - 1 (k from
+// generation_key_load; nsub <= 64) and shares the gBest key through LDS.
+// Workgroup 0 of the swarm (blk == 0) also records that key and the
+// improvement count in the trace ring and clears the group generation t + 1
+// will commit into.
 __device__ __forceinline__ unsigned long long generation_begin(const SwarmDev &S, uint32_t t,
-                                                               uint32_t blk)
+                                                               uint32_t blk,
+                                                               unsigned long long k)
 {
     __shared__ unsigned long long s_best;
     const uint32_t lane = threadIdx.x & 63u;
     if (threadIdx.x < 64u) {
         const uint32_t g = (t - 1u) % kGroups;
         const bool used = lane < S.nsub;
-        unsigned long long k = used ? *sub_key(S, g, lane) : ~0ull;
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) k = min_u64(k, shfl_xor_u64(k, m));
         if (lane == 0) s_best = k;
@@ -423,6 +435,12 @@ __device__ __forceinline__ unsigned long long generation_begin(const SwarmDev &S
     }
     __syncthreads();
     return s_best;
+}
+
+__device__ __forceinline__ unsigned long long generation_begin(const SwarmDev &S, uint32_t t,
+                                                               uint32_t blk)
+{
+    return generation_begin(S, t, blk, generation_key_load(S, t));
 }
 
 // End of generation t for one wave (no barrier): the wave's minimum key and
