@@ -91,20 +91,15 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     unsigned long long gkey = ~0ull;
     if constexpr (!INIT) gkey = generation_key_load(S, t);
 
-    uint32_t prow = 0;
-    bool alias = true;
+    // The state word and pBest fitness; the state is decoded only after the
+    // first row loads below have gone out, which do not depend on it.
+    uint32_t st = ST_ALIAS;  // pBest in row 0, position aliased (generation 0)
     float fpi = 0.0f;
     if (!INIT && valid) {
-        const uint32_t st = S.st[i];
+        st = S.st[i];
         fpi = S.fp[i];
-        prow = st & ST_ROW;
-        alias = (st & ST_ALIAS) != 0u;
     }
     const size_t ioff = (size_t)(valid ? i : 0u) * S.stride;
-    const f4 *p4 = reinterpret_cast<const f4 *>(S.rows + prow * S.buf + ioff);
-    f4 *x4 = reinterpret_cast<f4 *>(S.rows + (INIT ? 0u : (1u - prow)) * S.buf + ioff);
-    // Where the position is read from: the pBest row itself when aliased.
-    const f4 *xsrc = alias ? p4 : x4;
     const f4 *s4 = reinterpret_cast<const f4 *>(S.s);
 
     // Step m stages K-chunk m (lower half) and K-chunk HALF + m (upper half).
@@ -131,11 +126,14 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     const uint32_t cbase = 4u * HALF * half;  // first chunk of this wave's half
     const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
     f4 pv = zero4, xv = zero4, gv = zero4, sv = zero4;
+    // The first chunk is read from both rows at once, without waiting for
+    // the state word that says which row is the pBest (the same two loads).
+    f4 row0 = zero4, row1 = zero4;
     if (valid && cbase + lg < S.chunks) {
         sv = s4[cbase + lg];
         if constexpr (!INIT) {
-            pv = p4[cbase + lg];
-            xv = xsrc[cbase + lg];
+            row0 = reinterpret_cast<const f4 *>(S.rows + ioff)[cbase + lg];
+            row1 = reinterpret_cast<const f4 *>(S.rows + S.buf + ioff)[cbase + lg];
         }
     }
 
@@ -143,6 +141,15 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     // empty asm keeps them from being computed after the waits below).
     uint4 k_first = words4(S, cbase + lg, i, t);
     asm volatile("" : "+v"(k_first.x), "+v"(k_first.y), "+v"(k_first.z), "+v"(k_first.w));
+
+    const uint32_t prow = st & ST_ROW;
+    const bool alias = (st & ST_ALIAS) != 0u;
+    const f4 *p4 = reinterpret_cast<const f4 *>(S.rows + prow * S.buf + ioff);
+    f4 *x4 = reinterpret_cast<f4 *>(S.rows + (INIT ? 0u : (1u - prow)) * S.buf + ioff);
+    // Where the position is read from: the pBest row itself when aliased.
+    const f4 *xsrc = alias ? p4 : x4;
+    pv = prow ? row1 : row0;
+    xv = alias ? pv : (prow ? row0 : row1);
 
     const f4 *g4 = reinterpret_cast<const f4 *>(S.rows);
     if constexpr (!INIT) {
