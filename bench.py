@@ -14,8 +14,9 @@ Prints one JSON line:
   roofline = 12 algorithmic bytes per update (read x, read p, write x')
              / mean generation time, against 8 TB/s HBM3E (dense objective:
              2 N D^2 FLOP per generation against 157.3 TFLOP/s FP32 matrix)
-  cpu_baseline = the CPU oracle, single-threaded, on a few generations of the
-             same workload on this host.
+  cpu_baseline = the CPU oracle on a few generations of the same workload on
+             this host, on all the host threads it may use (its loops over
+             particles; same results), with the one-thread rate beside it.
 """
 from __future__ import annotations
 
@@ -124,7 +125,25 @@ def time_gpu_batch(swarms, steps, tune_gens):
     return ms, float(f.min()), gen, cpl, batch.mapping()[2]
 
 
-def time_oracle_batch(swarms, gens):
+def host_threads():
+    """Threads for the oracle's all-cores timing: OMP_NUM_THREADS where it is
+    set (the host's CPU share), else the CPUs this process may run on."""
+    n = int(os.environ.get("OMP_NUM_THREADS") or 0) or len(os.sched_getaffinity(0))
+    return max(1, n)
+
+
+def time_oracle_batch(swarms, gens, threads=1):
+    import oracle
+
+    used = oracle.set_threads(threads)
+    try:
+        updates, sec = _time_oracle_batch(swarms, gens)
+    finally:
+        oracle.set_threads(1)
+    return updates, sec, used
+
+
+def _time_oracle_batch(swarms, gens):
     import oracle
 
     sec = 0.0
@@ -141,16 +160,75 @@ def time_oracle_batch(swarms, gens):
     return updates, sec
 
 
-def time_oracle(wl, gens):
+def ceilings(reps=20):
+    """The two ceilings of the generation kernels, measured on this GPU: a
+    plain device-to-device copy (HBM read + write bandwidth) and the rate of
+    the library's Philox kernel, which draws every word of one generation of
+    the ripple swarm's shape (4 words per Philox4x32-10 block) and writes each
+    word to HBM (4 B per word)."""
+    import torch
+
+    from paper_2110_01470_amd.binding import Swarm
+    from paper_2110_01470_amd.inputs import WORKLOADS
+
+    stream = torch.cuda.Stream()
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            dst.copy_(src)
+        e0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record(stream)
+    e1.synchronize()
+    copy_s = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+
+    wl = WORKLOADS["ripple_n65536_d1000"]
+    s, w, a = wl.objective()
+    sw = Swarm(wl.n, wl.d, wl.kind, wl.lo, wl.hi, wl.cg, wl.cp, wl.cw, wl.seed, s, w, a,
+               stream=stream)
+    out = torch.empty(wl.n * wl.d, dtype=torch.int32, device="cuda")
+    sw.rng_words_into(1, out, 3)
+    e0.record(stream)
+    sw.rng_words_into(1, out, reps)
+    e1.record(stream)
+    e1.synchronize()
+    rng_s = e0.elapsed_time(e1) / 1e3 / reps
+    words = wl.n * wl.d
+    print(json.dumps({
+        "ceilings": {
+            "copy": {"bytes": nbytes, "us_per_copy": copy_s * 1e6,
+                     "GBps_read_plus_write": 2 * nbytes / copy_s / 1e9,
+                     "frac_of_peak": 2 * nbytes / copy_s / 1e9 / HBM_PEAK_GBS},
+            "philox": {"words_per_launch": words, "us_per_launch": rng_s * 1e6,
+                       "words_per_s": words / rng_s,
+                       "write_GBps": 4 * words / rng_s / 1e9,
+                       "note": f"one generation's words of {wl.name}, each written to HBM"},
+        }}), flush=True)
+
+
+def time_oracle(wl, gens, threads=1):
+    """Seconds for `gens` oracle generations after initialisation, and the
+    thread count the oracle used."""
     import oracle
 
     kind = {"sphere": oracle.SPHERE, "ripple": oracle.RIPPLE, "dense": oracle.DENSE}[wl.kind]
     s, w, a = wl.objective()
-    orc = oracle.Swarm(wl.n, wl.d, kind, wl.lo, wl.hi, wl.cg, wl.cp, wl.cw, wl.seed, s, w, a)
-    orc.init()
-    t0 = time.perf_counter()
-    orc.run(gens)
-    return time.perf_counter() - t0
+    used = oracle.set_threads(threads)
+    try:
+        orc = oracle.Swarm(wl.n, wl.d, kind, wl.lo, wl.hi, wl.cg, wl.cp, wl.cw, wl.seed, s, w, a)
+        orc.init()
+        t0 = time.perf_counter()
+        orc.run(gens)
+        sec = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(1)
+    return sec, used
 
 
 def copy_calibration(nbytes, reps=5):
@@ -188,12 +266,17 @@ def main():
     ap.add_argument("--engine", default="auto", choices=["auto", "stream", "resident"])
     ap.add_argument("--cpu-gens", type=int, default=None,
                     help="oracle generations for cpu_baseline (0 = skip)")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="only measure the copy-bandwidth and Philox-rate ceilings")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
 
     if args.copy_bytes:
         copy_calibration(args.copy_bytes)
+        return
+    if args.ceilings:
+        ceilings()
         return
 
     if args.gpus != 1:
@@ -245,12 +328,19 @@ def main():
             cpu_gens = max(1, min(steps, 4 * 16384 * 256 // (wl.n * wl.d)))
     cpu = None
     if cpu_gens > 0:
-        csec = time_oracle(wl, cpu_gens)
-        cpu = {"value": wl.n * wl.d * cpu_gens / csec, "unit": "particle-var updates/s",
-               "cores": 1, "kind": "oracle",
-               "sample": f"{cpu_gens} generations of {wl.name} after initialisation, "
-                         f"single-threaded FP64 oracle, {csec:.2f} s"}
-        log(f"cpu oracle: {csec:.2f} s for {cpu_gens} generations")
+        csec1, _ = time_oracle(wl, cpu_gens)
+        log(f"cpu oracle, one thread: {csec1:.2f} s for {cpu_gens} generations")
+        nth = host_threads()
+        gens_n = min(steps, max(cpu_gens, cpu_gens * nth // 2))
+        csec, used = time_oracle(wl, gens_n, nth)
+        log(f"cpu oracle, {used} threads: {csec:.2f} s for {gens_n} generations")
+        upd = wl.n * wl.d
+        cpu = {"value": upd * gens_n / csec, "unit": "particle-var updates/s",
+               "cores": used, "kind": "oracle",
+               "sample": f"{gens_n} generations of {wl.name} after initialisation, FP64 oracle "
+                         f"on {used} threads ({csec:.2f} s); one thread: {cpu_gens} "
+                         f"generations ({csec1:.2f} s)",
+               "single_thread": {"value": upd * cpu_gens / csec1, "cores": 1}}
 
     rec = {
         "metric": "particle-var updates/s incl. fitness",
@@ -536,12 +626,18 @@ def bench_batch(bw, args):
     cpu = None
     if args.cpu_gens is None or args.cpu_gens > 0:
         gens = args.cpu_gens or 1
-        updates, csec = time_oracle_batch(swarms, gens)
-        cpu = {"value": updates / csec, "unit": "particle-var updates/s", "cores": 1,
+        updates1, csec1, _ = time_oracle_batch(swarms, gens)
+        log(f"cpu oracle, one thread: {csec1:.2f} s for {updates1} updates")
+        nth = host_threads()
+        gens_n = max(gens, gens * nth // 8)
+        updates, csec, used = time_oracle_batch(swarms, gens_n, nth)
+        log(f"cpu oracle, {used} threads: {csec:.2f} s for {updates} updates")
+        cpu = {"value": updates / csec, "unit": "particle-var updates/s", "cores": used,
                "kind": "oracle",
-               "sample": f"{gens} generation(s) of each of the {bw.count} swarms of {bw.name} "
-                         f"after initialisation, single-threaded FP64 oracle, {csec:.2f} s"}
-        log(f"cpu oracle: {csec:.2f} s for {updates} updates")
+               "sample": f"{gens_n} generation(s) of each of the {bw.count} swarms of {bw.name} "
+                         f"after initialisation, FP64 oracle on {used} threads ({csec:.2f} s); "
+                         f"one thread: {gens} generation(s) ({csec1:.2f} s)",
+               "single_thread": {"value": updates1 / csec1, "cores": 1}}
     rec = {
         "metric": "particle-var updates/s incl. fitness",
         "value": total * steps / sec,

@@ -117,8 +117,20 @@ def _load():
     lib.orc_dense_grad.restype = None
     lib.orc_polish.argtypes = [ctypes.POINTER(_Swarm), u32, f64]
     lib.orc_polish.restype = ctypes.c_int
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_threads.restype = None
+    lib.orc_threads.argtypes = []
+    lib.orc_threads.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def set_threads(n):
+    """Threads for the oracle's loops over particles; returns the count in
+    use (results do not depend on it)."""
+    lib = _load()
+    lib.orc_set_threads(int(n))
+    return int(lib.orc_threads())
 
 
 def _ptr(a):

@@ -8,8 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # ORACLE_LIB points the tests at another build (the mutation tests use it).
 LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 SOURCES = [os.path.join(HERE, "sso_oracle.c")]
-CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-          "-Wall", "-Wextra"]
+CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+          "-shared", "-Wall", "-Wextra"]
 
 
 def build(out: str = LIB_PATH, extra=(), sources=None) -> str:

@@ -6,14 +6,31 @@
  * code with the GPU path.  Plain loops, no blocking, no fusion: each function
  * follows one passage of the paper and says which.
  *
- * Build: gcc -std=c11 -O2 -ffp-contract=off -fPIC -shared (no -march flags, so
- * no FMA contraction can creep into the FP64 fitness).
+ * Build: gcc -std=c11 -O2 -ffp-contract=off -fopenmp -fPIC -shared (no -march
+ * flags, so no FMA contraction can creep into the FP64 fitness).  The loops
+ * over particles may run on several threads (orc_set_threads; one by
+ * default): every particle's work reads only the previous generation's state
+ * and writes only its own row, and the argmin stays serial, so the results do
+ * not depend on the thread count.
  */
 #include "sso_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+
+static int g_threads = 1;
+
+void orc_set_threads(int n) { g_threads = n > 0 ? n : 1; }
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return g_threads;
+#else
+    return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------------------
  * Philox4x32-10, from its published definition (Salmon, Moraes, Dror, Shaw,
@@ -60,6 +77,7 @@ void orc_words(uint64_t seed, uint32_t swarm, uint32_t t, uint32_t n, uint32_t d
                uint32_t *out)
 {
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#pragma omp parallel for num_threads(g_threads) schedule(static)
     for (uint32_t i = 0; i < n; ++i) {
         for (uint32_t j = 0; j < d; ++j) {
             uint32_t ctr[4] = {j / 4u, i, t, swarm};
@@ -418,6 +436,7 @@ void orc_init_with_words(orc_swarm *sw, const uint32_t *words)
     for (size_t e = 0; e < nd; ++e)
         sw->x[e] = orc_init_value(&sw->rule, words[e]);
     memcpy(sw->p, sw->x, sizeof(float) * nd);
+#pragma omp parallel for num_threads(g_threads) schedule(static)
     for (uint32_t i = 0; i < sw->n; ++i) {
         double f = fitness_of(sw, sw->x + (size_t)i * sw->d);
         sw->fx64[i] = f;
@@ -437,6 +456,7 @@ void orc_generation_with_words(orc_swarm *sw, const uint32_t *words)
      * (i, j) reads only x_ij, p_ij and g_j, none of which this loop changes
      * for another element, so updating x in place is the same as reading a
      * frozen copy. */
+#pragma omp parallel for num_threads(g_threads) schedule(static)
     for (uint32_t i = 0; i < n; ++i) {
         for (uint32_t j = 0; j < d; ++j) {
             size_t e = (size_t)i * d + j;
@@ -450,6 +470,7 @@ void orc_generation_with_words(orc_swarm *sw, const uint32_t *words)
         }
     }
     /* Evaluate, then Algorithm 3: replace the pBest on a strict improvement. */
+#pragma omp parallel for num_threads(g_threads) schedule(static)
     for (uint32_t i = 0; i < n; ++i) {
         const float *xi = sw->x + (size_t)i * d;
         double f = fitness_of(sw, xi);

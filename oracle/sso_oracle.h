@@ -155,6 +155,12 @@ int orc_polish(orc_swarm *sw, uint32_t steps, double lr);
 /* Index of the smallest fp (NaN above everything), lowest index on ties. */
 uint32_t orc_argmin(uint32_t n, const float *fp);
 
+/* Threads for the loops over particles (default 1; values below 1 mean 1).
+ * The results are the same for any count.  orc_threads() reports the count
+ * in use: always 1 in a build without OpenMP. */
+void orc_set_threads(int n);
+int orc_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -255,6 +255,24 @@ class Swarm:
                 tns.record_stream(self.stream)
         return fo, go
 
+    def rng_words_into(self, t, out, count=1):
+        """Enqueue the device's Philox words of generations t .. t + count - 1
+        into `out` (each overwriting the last), an int32 device tensor of
+        n * d elements, on the swarm's stream, ordered after the work already
+        queued on the current stream (no host wait).  count > 1 keeps the
+        launches back to back, for timing the word kernel."""
+        import torch
+
+        if out.numel() != self.n * self.d or out.dtype.itemsize != 4 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous 4-byte tensor of n * d elements")
+        cur = torch.cuda.current_stream(out.device)
+        self.stream.wait_stream(cur)
+        ptr = ctypes.c_void_p(out.data_ptr())
+        for k in range(count):
+            self._check(self._lib.sso_debug_rng(self._ctx, t + k, ptr))
+        cur.wait_stream(self.stream)
+        out.record_stream(self.stream)
+
     def debug_rng(self, t):
         """The device's Philox words of generation t, as an [n, d] uint32 array."""
         import torch

@@ -120,28 +120,34 @@ int launch_fill_trace(const SwarmDev &S, void *stream)
     return (int)hipGetLastError();
 }
 
-// The word of every (particle, variable) at generation t, as the kernels draw it.
-__global__ void k_debug_rng(SwarmDev S, uint32_t t, uint32_t *out)
+// The word of every (particle, variable) at generation t, as the kernels draw
+// it.  Lane l of wave w in block (bx, by) owns chunk 64 bx + l of particles
+// 4 by + w, 4 (by + gridDim.y) + w, ...; with vec (d a multiple of 4 and
+// out 16-byte aligned) a chunk is one 16-byte store.
+__global__ __launch_bounds__(256) void k_debug_rng(SwarmDev S, uint32_t t, uint32_t *out,
+                                                   bool vec)
 {
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t total = (uint64_t)S.n * S.chunks;
-    if (e >= total) return;
-    const uint32_t i = (uint32_t)(e / S.chunks), c = (uint32_t)(e % S.chunks);
-    const uint4 k = words4(S, c, i, t);
-    const uint32_t v[4] = {k.x, k.y, k.z, k.w};
+    const uint32_t c = blockIdx.x * 64u + (threadIdx.x & 63u);
+    if (c >= S.chunks) return;
+    for (uint32_t i = blockIdx.y * 4u + (threadIdx.x >> 6); i < S.n; i += gridDim.y * 4u) {
+        const uint4 k = words4(S, c, i, t);
+        uint32_t *row = out + (uint64_t)i * S.d;
+        if (vec) {
+            reinterpret_cast<uint4 *>(row)[c] = k;
+        } else {
+            const uint32_t v[4] = {k.x, k.y, k.z, k.w};
 #pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) {
-        const uint32_t j = 4u * c + q;
-        if (j < S.d) out[(uint64_t)i * S.d + j] = v[q];
+            for (uint32_t q = 0; q < 4; ++q)
+                if (4u * c + q < S.d) row[4u * c + q] = v[q];
+        }
     }
 }
 
 int launch_debug_rng(const SwarmDev &S, uint32_t t, uint32_t *out, void *stream)
 {
-    const uint64_t total = (uint64_t)S.n * S.chunks;
-    const uint64_t blocks = (total + 255u) / 256u;
-    hipLaunchKernelGGL(k_debug_rng, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, S,
-                       t, out);
+    const dim3 grid((S.chunks + 63u) / 64u, std::min<uint32_t>((S.n + 3u) / 4u, 65535u));
+    const bool vec = (S.d & 3u) == 0u && (reinterpret_cast<uintptr_t>(out) & 15u) == 0u;
+    hipLaunchKernelGGL(k_debug_rng, grid, dim3(256), 0, (hipStream_t)stream, S, t, out, vec);
     return (int)hipGetLastError();
 }
 

@@ -31,6 +31,24 @@ def test_device_words_match_oracle(n, d, t, swarm):
     assert np.array_equal(got, oracle.words(0x1234_5678_9ABC_DEF0, swarm, t, n, d))
 
 
+@pytest.mark.parametrize("n,d,offset", [(262150, 4, 0), (40, 1000, 0), (9, 8, 1), (33, 12, 2)])
+def test_device_words_grid_and_store_paths(n, d, offset):
+    """The word kernel's grid-stride loop over particles (n above 4 * 65535),
+    several chunk blocks per row, and the scalar stores taken when the
+    output is not 16-byte aligned."""
+    import torch
+
+    pair = Pair("sphere", n, d, seed=77, swarm_id=5)
+    buf = torch.full((n * d + offset,), -1, dtype=torch.int32, device="cuda")
+    out = buf[offset:]
+    pair.gpu.rng_words_into(9, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32).reshape(n, d)
+    assert np.array_equal(got, oracle.words(77, 5, 9, n, d))
+    if offset:
+        assert np.all(buf[:offset].cpu().numpy() == -1)
+
+
 @pytest.mark.parametrize("kind,n,d,engine", [
     ("sphere", 100, 30, "resident"), ("sphere", 100, 30, "stream"),
     ("ripple", 301, 1000, "stream"), ("ripple", 33, 61, "resident"),

@@ -213,3 +213,35 @@ def test_lowest_index_wins_exact_ties():
     assert oracle.argmin(np.array([3, np.nan, 1, 1, np.inf], np.float32)) == 2
     assert oracle.argmin(np.array([np.nan, np.nan], np.float32)) == 0
     assert oracle.argmin(np.array([np.nan, np.inf], np.float32)) == 1
+
+
+@pytest.mark.parametrize("kind", ["ripple", "dense", "f3"])
+def test_thread_count_does_not_change_results(kind):
+    """The loops over particles may run on several threads (the all-cores
+    timing of the CPU baseline): a run on 4 threads is bit-identical to a run
+    on one."""
+    n, d = 203, 37
+    states = []
+    for threads in (1, 4):
+        assert oracle.set_threads(threads) == threads
+        try:
+            if kind == "f3":
+                sw = oracle.Swarm(n, d, oracle.F3, -100.0, 100.0, 0.8, 0.6, 0.3, 9, None,
+                                  order=oracle.ORDER_EQ21)
+                sw.init().run(6)
+            else:
+                sw, *_ = make_swarm(kind, n, d, 57)
+                sw.init().run(6)
+            states.append((sw.x.copy(), sw.p.copy(), sw.fp.copy(), sw.fp64.copy(), sw.g.copy(),
+                           sw.gidx, sw.improved.copy()))
+        finally:
+            oracle.set_threads(1)
+    for u, v in zip(*states):
+        assert np.array_equal(u, v)
+    w1 = oracle.words(3, 0, 5, 40, 9)
+    oracle.set_threads(4)
+    try:
+        w4 = oracle.words(3, 0, 5, 40, 9)
+    finally:
+        oracle.set_threads(1)
+    assert np.array_equal(w1, w4)
