@@ -122,7 +122,44 @@ def time_gpu_batch(swarms, steps, tune_gens):
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
     f, gi, im, gen = batch.results()
-    return ms, float(f.min()), gen, cpl, batch.mapping()[2]
+    _, lanes, tiles = batch.mapping()
+    return ms, f, gen, cpl, tiles, lanes
+
+
+def time_gpu_separate(swarms, steps, lanes):
+    """Plain SSO for the batch's swarms: one one-swarm context per swarm, each
+    run for `steps` generations in turn on one stream (the way the swarms
+    would run without batching).  A swarm whose batch lanes the one-swarm
+    engine takes (8 or more) is given those lanes, so its run is
+    bit-identical to its run in the batch; the others take the engine's own
+    choice.  Returns the milliseconds, each swarm's final gBest fitness, and
+    which swarms had the batch's lanes."""
+    import torch
+
+    from paper_2110_01470_amd.binding import Swarm
+
+    stream = torch.cuda.Stream()
+    sws, same = [], []
+    for k, sw in enumerate(swarms):
+        ln = int(lanes[k]) if lanes[k] >= 8 else 0
+        same.append(ln != 0)
+        sws.append(Swarm(sw["n"], sw["d"], sw["kind"], sw["lo"], sw["hi"], sw["cg"], sw["cp"],
+                         sw["cw"], sw["seed"], sw["s"], sw["w"], swarm_id=sw["swarm_id"],
+                         order=sw.get("order", 0), storage=sw.get("storage", "auto"), lanes=ln,
+                         engine="stream", stream=stream))
+    stream.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for s in sws:
+        s.run(steps)
+    stop.record(stream)
+    stop.synchronize()
+    ms = start.elapsed_time(stop)
+    f = np.array([s.best()[1] for s in sws], dtype=np.float32)
+    for s in sws:
+        s.close()
+    return ms, f, np.array(same)
 
 
 def host_threads():
@@ -261,6 +298,9 @@ def main():
     ap.add_argument("--polish", action="store_true",
                     help="dense workload: time-to-gap of plain SSO vs SSO with a gradient "
                          "polish of all pBests every 50 generations")
+    ap.add_argument("--separate", action="store_true",
+                    help="batch workload: also run every swarm alone (plain SSO, one context "
+                         "per swarm) for the same generations and compare")
     ap.add_argument("--tune-gens", type=int, default=5,
                     help="generations the batch mapping tuner times per candidate")
     ap.add_argument("--engine", default="auto", choices=["auto", "stream", "resident"])
@@ -615,10 +655,22 @@ def bench_batch(bw, args):
     swarms = bw.swarms()
     total = sum(sw["n"] * sw["d"] for sw in swarms)
     log(f"workload {bw.name}: {bw.count} swarms, {total} variables, steps={steps}")
-    ms, fbest, gen, cpl, tiles = time_gpu_batch(swarms, steps, args.tune_gens)
+    ms, fb, gen, cpl, tiles, lanes = time_gpu_batch(swarms, steps, args.tune_gens)
     sec = ms / 1e3
     ms_per_step = ms / steps
-    log(f"gpu: {ms:.3f} ms for {steps} generations, best fG over swarms={fbest:.6g} at t={gen}")
+    log(f"gpu: {ms:.3f} ms for {steps} generations, best fG over swarms={float(fb.min()):.6g} "
+        f"at t={gen}")
+    separate = None
+    if args.separate:
+        ms_sep, fs, same = time_gpu_separate(swarms, steps, lanes)
+        log(f"separate swarms: {ms_sep:.3f} ms for {steps} generations")
+        rel = np.abs(fs.astype(np.float64) - fb) / np.maximum(np.abs(fb.astype(np.float64)), 1e-30)
+        separate = {"ms_per_step": ms_sep / steps, "speedup_of_batch": ms_sep / ms,
+                    "swarms_with_batch_lanes": int(same.sum()),
+                    "equal_final_fG_with_batch_lanes": int(np.sum(fs[same] == fb[same])),
+                    "max_rel_final_fG_diff_other": float(rel[~same].max()) if (~same).any() else 0.0,
+                    "note": "each swarm run alone with the one-swarm library, "
+                            "the swarms one after another on one stream"}
     byt = BYTES_PER_UPDATE * total
     achieved = byt / (ms_per_step / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -657,6 +709,8 @@ def bench_batch(bw, args):
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if separate is not None:
+        rec["separate_swarms"] = separate
     print(json.dumps(rec), flush=True)
 
 
