@@ -225,3 +225,47 @@ def test_polished_run_keeps_invariants_and_beats_plain():
     g, f, gidx, _ = pol.best()
     assert f == fp.min() and gidx == int(np.argmin(fp)) and np.array_equal(g, p[gidx])
     assert f < plain.best()[1]
+
+
+def test_polish_full_size_sampled():
+    """The dense workload at full size (N=16384, D=256) and the benchmark's
+    polish (5 steps, default step size): the polish of a particle depends
+    only on its own pBest, so 64 sampled particles are polished by the oracle
+    from the GPU's pBests and compared to the bar of polish_both; gBest is
+    checked against all 16384 pBest fitnesses."""
+    wl = WORKLOADS["dense_n16384_d256"]
+    s, _, a = wl.objective()
+    from paper_2110_01470_amd.binding import Swarm
+
+    sw = Swarm(wl.n, wl.d, "dense", wl.lo, wl.hi, wl.cg, wl.cp, wl.cw, wl.seed, s, None, a)
+    sw.run(3)
+    x0, p0, fp0, t0 = sw.state()
+    used = sw.polish(5, 0.0)
+    x1, p1, fp1, t1 = sw.state()
+    assert t1 == t0 and np.array_equal(x1, x0)
+    rng = np.random.default_rng(17)
+    idx = np.unique(np.concatenate([[0, 1, 63, 64, wl.n - 1],
+                                    rng.choice(wl.n, 59, replace=False)]))
+    orc = oracle.Swarm(len(idx), wl.d, oracle.DENSE, wl.lo, wl.hi, wl.cg, wl.cp, wl.cw, wl.seed,
+                       s, None, a)
+    orc.init()
+    orc.set_state(x0[idx], p0[idx], fp0[idx], t0)
+    fp0_64 = orc.fp64.copy()
+    orc.polish(5, float(used))
+    ulp = np.spacing(np.float32(max(abs(wl.lo), abs(wl.hi))))
+    ties = 0
+    for r, i in enumerate(idx):
+        imp_g = bool(np.any(p1[i] != p0[i]) or fp1[i] != fp0[i])
+        if bool(orc.improved[r]) != imp_g:
+            assert near(orc.fx64[r], fp0_64[r]), f"accept decision of {i} differs outside the band"
+            ties += 1
+            continue
+        if imp_g:
+            assert np.max(np.abs(p1[i] - orc.p[r])) <= 16 * 5 * ulp
+            assert abs(fp1[i] - orc.fp64[r]) <= REL_TOL * abs(orc.fp64[r])
+        else:
+            assert np.array_equal(p1[i], p0[i]) and fp1[i] == fp0[i]
+    assert ties <= 2
+    g, fg, gidx, _ = sw.best()
+    assert fg == fp1.min() and gidx == int(np.argmin(fp1)) and np.array_equal(g, p1[gidx])
+    assert np.all(fp1 <= fp0)
