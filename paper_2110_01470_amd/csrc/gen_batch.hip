@@ -22,9 +22,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_batch(BatchDev B, uint32_t j)
     const SwarmDev S = B.table[sw];
     const uint32_t t = INIT ? 0u : *B.tbase + j;
     if (S.d & 3u)
-        stream_body<KIND, 0, EQ21, INIT, true, true, Store>(S, t, blk, S.lanes);
+        stream_body<KIND, 0, EQ21, INIT, true, true, Store, false>(S, t, blk, S.lanes);
     else
-        stream_body<KIND, 0, EQ21, INIT, false, true, Store>(S, t, blk, S.lanes);
+        stream_body<KIND, 0, EQ21, INIT, false, true, Store, false>(S, t, blk, S.lanes);
 }
 
 // Trace ring and sub-slot groups of swarm blockIdx.x to "nothing yet".

@@ -48,7 +48,15 @@ inline size_t stage_bytes(const SwarmDev &S)
 // STAGE: the shift, the ripple weights and the gBest row are copied into LDS
 // once per workgroup (dynamic LDS, see stage_bytes) and read from there, so
 // the vector-memory path carries only the particle's own pBest and position.
-template <int KIND, int LT, bool EQ21, bool INIT, bool RAGGED, bool STAGE, class Store>
+// EARLY: the start of a generation is ordered for latency -- the gBest key
+// is loaded before everything else, and a lane's first chunk is read from
+// both rows without waiting for the state word (one dependent latency fewer;
+// an aliased particle then reads one chunk more).  4 % faster on swarms
+// small enough to be latency-bound (Table 3.2 functions, N <= 350, D = 50);
+// the batched kernel, whose many short workgroups overlap one another, runs
+// faster without it (567 vs 569-572 us per generation of the 512 swarms).
+template <int KIND, int LT, bool EQ21, bool INIT, bool RAGGED, bool STAGE, class Store,
+          bool EARLY = true>
 __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint32_t blk,
                                             uint32_t l)
 {
@@ -64,17 +72,37 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
     const uint32_t i = ((blk * kWaves + wave) << (6u - lsh)) + (lane >> lsh);
     const bool valid = i < S.n;
 
+    // With EARLY the gBest key load goes out first (see generation_key_load).
+    unsigned long long gkey = ~0ull;
+    if constexpr (!INIT && EARLY) gkey = generation_key_load(S, t);
+    // The state word and pBest fitness; with EARLY the state is decoded only
+    // after the first row loads below have gone out, which do not depend on it.
+    uint32_t st = ST_ALIAS;  // pBest in row 0, position aliased (generation 0)
+    float fpi = 0.0f;
     uint32_t prow = 0;
     bool alias = true;
-    float fpi = 0.0f;
     if (!INIT && valid) {
-        const uint32_t st = S.st[i];
+        st = S.st[i];
         fpi = S.fp[i];
-        prow = st & ST_ROW;
-        alias = (st & ST_ALIAS) != 0u;
+        if constexpr (!EARLY) {
+            prow = st & ST_ROW;
+            alias = (st & ST_ALIAS) != 0u;
+        }
     }
     uint32_t *rows = reinterpret_cast<uint32_t *>(S.rows);
     const size_t ioff = (size_t)(valid ? i : 0u) * S.stride;
+    // This lane's first chunk of both rows, as stored (unpacked when the
+    // chunk is computed): the same two loads as pBest and position, issued
+    // without waiting for the state word that tells which is which.
+    typename Store::R r0{}, r1{};
+    if (EARLY && !INIT && valid && ln < S.chunks) {
+        r0 = Store::load_raw(rows + ioff, ln);
+        r1 = Store::load_raw(rows + S.buf + ioff, ln);
+    }
+    if constexpr (EARLY) {
+        prow = st & ST_ROW;
+        alias = (st & ST_ALIAS) != 0u;
+    }
     const uint32_t *prow_ptr = rows + prow * S.buf + ioff;
     // INIT writes the pBest row (row 0); a generation writes the other row.
     uint32_t *xrow_ptr = rows + (INIT ? 0u : (1u - prow)) * S.buf + ioff;
@@ -88,8 +116,7 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
     uint32_t *lg = reinterpret_cast<uint32_t *>(lds_dyn + staged_arrays<KIND>() * S.chunks);
 
     // Loads that do not depend on gBest go out before the start-of-generation
-    // barrier: the shift and weights for staging, this lane's first pBest and
-    // position (as stored; unpacked when the chunk is computed).
+    // barrier: the shift and weights for staging.
     if constexpr (STAGE && KIND != OBJ_PAPER) {
         for (uint32_t q = tid; q < S.chunks; q += blockDim.x) {
             ls[q] = s4[q];
@@ -97,14 +124,18 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
         }
     }
     typename Store::R pr{}, xr{};
-    if (!INIT && valid && ln < S.chunks) {
+    if constexpr (EARLY) {
+        pr = prow ? r1 : r0;
+        xr = alias ? pr : (prow ? r0 : r1);
+    } else if (!INIT && valid && ln < S.chunks) {
         pr = Store::load_raw(prow_ptr, ln);
         xr = Store::load_raw(xsrc, ln);
     }
     // gBest of the previous generation (unused at t == 0).
     const uint32_t *grow_ptr = nullptr;
     if constexpr (!INIT) {
-        const uint32_t glow = (uint32_t)generation_begin(S, t, blk);
+        const uint32_t glow = EARLY ? (uint32_t)generation_begin(S, t, blk, gkey)
+                                    : (uint32_t)generation_begin(S, t, blk);
         const uint32_t gidx = min(glow >> 1, S.n - 1u);
         grow_ptr = rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.stride;
         if constexpr (STAGE) {
