@@ -19,8 +19,13 @@
 //     projected step happens in registers.
 //  3. f = sum_k y_k^2 over the full Y^T, summed as the generation kernel
 //     sums it.
-// A and A^T (256 KB each at D=256) stay in L2; each wave reads its operands
-// straight from global memory.
+// A and A^T (256 KB each at D=256) stay in L2 and reach the waves through
+// LDS: a polish step is a sequence of stages of two K-chunks each (HALF
+// stages of A for the residual, both halves' chunks at once; NB/2 stages of
+// A^T, two row blocks each, for the gradient).  Every stage is copied into
+// one of two LDS buffers by global-to-LDS loads while the waves contract the
+// stage before it, so each operand crosses from L2 once per workgroup, not
+// once per particle group.
 #include "sso_device.hpp"
 
 namespace sso {
@@ -37,7 +42,15 @@ __global__ __launch_bounds__(kGradBlock) void k_dense_grad(SwarmDev S, GradArgs 
 {
     constexpr uint32_t HALF = NB / 2;
     constexpr uint32_t CF4 = NB * 64u;  // float4 per K-chunk of a packed matrix
+    constexpr uint32_t STAGE_F4 = 2 * CF4;  // one stage: two K-chunks
+    constexpr uint32_t PER = (STAGE_F4 + kGradBlock - 1) / kGradBlock;
+    constexpr bool FULL = STAGE_F4 % kGradBlock == 0;
     __shared__ f4 red[4 * NB * 64];
+    // Two stage buffers as two variables, so that the compiler tells the
+    // reads of one from the copies in flight into the other.
+    __shared__ f4 lds0[STAGE_F4];
+    __shared__ f4 lds1[STAGE_F4];
+    __shared__ f4 s_lds[NB * 4];  // the shift, dp / 4 chunks (zero past d)
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u, wave = tid >> 6;
@@ -51,6 +64,31 @@ __global__ __launch_bounds__(kGradBlock) void k_dense_grad(SwarmDev S, GradArgs 
     const f4 *s4 = reinterpret_cast<const f4 *>(S.s);
     const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
     const uint32_t cbase = 4u * HALF * half;  // chunk of m = 0; chunk of m is cbase + 4 m + lg
+
+    // Stage q < HALF: K-chunks q (lower half) and HALF + q (upper half) of A,
+    // the residual's step q.  Stage q >= HALF: row blocks 2 (q - HALF) and
+    // 2 (q - HALF) + 1 of A^T (each a whole packed K-chunk), the gradient's
+    // step q - HALF.  Stage q goes to buffer q mod 2.
+    auto stage_dma = [&](uint32_t q, uint32_t b) {
+        // The copy addresses are the same at every polish step; opaque bases
+        // keep the compiler from hoisting all of them out of the step loop
+        // (they do not fit in registers).
+        const f4 *ap = a_pack, *atp = at_pack;
+        asm volatile("" : "+s"(ap), "+s"(atp));
+#pragma unroll
+        for (uint32_t r = 0; r < PER; ++r) {
+            const uint32_t e = tid + r * kGradBlock;
+            if (FULL || e < STAGE_F4) {
+                const f4 *src = q < HALF ? ap + (size_t)(e < CF4 ? q : HALF + q) * CF4 + (e % CF4)
+                                         : atp + (size_t)(2u * (q - HALF)) * CF4 + e;
+                __builtin_amdgcn_global_load_lds(
+                    (const void *)src,
+                    (__attribute__((address_space(3))) void *)(&(b ? lds1 : lds0)[r * kGradBlock + wave * 64u]),
+                    16, 0, 0);
+            }
+        }
+    };
+    stage_dma(0, 0);
 
     // The point, chunk by chunk (columns >= d are masked where used).
     f4 pc[HALF];
@@ -88,29 +126,35 @@ __global__ __launch_bounds__(kGradBlock) void k_dense_grad(SwarmDev S, GradArgs 
         pc[m] = v;
     }
 
+    // The shift into LDS: its reads then wait on the LDS counter only, not on
+    // the copies in flight.
+    for (uint32_t c = tid; c < NB * 4u; c += kGradBlock) s_lds[c] = c < S.chunks ? s4[c] : zero4;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copy of stage 0 has landed
+    __syncthreads();
+
     f4 acc[NB];
-    // acc = the full Y^T of the current point (both halves).
-    auto residual = [&]() {
-        // The matrix operands are the same at every polish step; an opaque
-        // pointer keeps the compiler from hoisting all of them out of the
-        // step loop (they do not fit in registers).
-        const f4 *ap = a_pack;
-        asm volatile("" : "+s"(ap));
+    // acc = the full Y^T of the current point (both halves).  grad_next: a
+    // gradient follows, so its first stage is copied during the last one here.
+    auto residual = [&](bool grad_next) {
 #pragma unroll
         for (uint32_t rb = 0; rb < NB; ++rb) acc[rb] = zero4;
 #pragma unroll
         for (uint32_t m = 0; m < HALF; ++m) {
+            const uint32_t cur = m & 1u;
             const uint32_t c = cbase + 4u * m + lg;
             f4 dv = zero4;
             if (valid && c < S.chunks) {
-                const f4 sv = s4[c];
+                const f4 sv = s_lds[c];
                 const uint32_t j0 = 4u * c;
                 dv.x = (j0 + 0 < S.d) ? pc[m].x - sv.x : 0.f;
                 dv.y = (j0 + 1 < S.d) ? pc[m].y - sv.y : 0.f;
                 dv.z = (j0 + 2 < S.d) ? pc[m].z - sv.z : 0.f;
                 dv.w = (j0 + 3 < S.d) ? pc[m].w - sv.w : 0.f;
             }
-            const f4 *la = ap + (size_t)(HALF * half + m) * CF4 + lane;
+            const bool copy = m + 1 < HALF || grad_next;
+            if (copy) stage_dma(m + 1, cur ^ 1u);  // stage HALF is the gradient's first
+            __builtin_amdgcn_sched_barrier(0);
+            const f4 *la = (cur ? lds1 : lds0) + half * CF4 + lane;
             // Row blocks in groups of four: four independent accumulators
             // between dependent MFMAs, 16 registers of A operands.
 #pragma unroll
@@ -124,9 +168,10 @@ __global__ __launch_bounds__(kGradBlock) void k_dense_grad(SwarmDev S, GradArgs 
                     for (uint32_t q = 0; q < 4 && r0 + q < NB; ++q)
                         acc[r0 + q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q][e], dv[e], acc[r0 + q], 0, 0, 0);
             }
+            if (copy) __builtin_amdgcn_s_waitcnt(0);  // this wave's copy has landed
+            __syncthreads();
         }
         f4 *r = red + (size_t)grp4 * NB * 64u + lane;
-        __syncthreads();  // the previous exchange has been read
         if (half == 1) {
 #pragma unroll
             for (uint32_t rb = 0; rb < NB; ++rb) r[rb * 64u] = acc[rb];
@@ -147,24 +192,33 @@ __global__ __launch_bounds__(kGradBlock) void k_dense_grad(SwarmDev S, GradArgs 
     };
 
     // gr[jj] = (A^T Y^T) for output block HALF * half + jj: half the gradient
-    // of this lane's chunk jj.
+    // of this lane's chunk jj.  res_next: a residual follows, so its first
+    // stage is copied during the last one here.
     f4 gr[HALF];
-    auto gradient = [&]() {
-        const f4 *atp = at_pack;
-        asm volatile("" : "+s"(atp));
+    auto gradient = [&](bool res_next) {
 #pragma unroll
         for (uint32_t jj = 0; jj < HALF; ++jj) gr[jj] = zero4;
 #pragma unroll
-        for (uint32_t rb = 0; rb < NB; ++rb) {
-            const f4 *la = atp + (size_t)rb * CF4 + (size_t)(HALF * half) * 64u + lane;
-            f4 av[HALF];
+        for (uint32_t g = 0; g < NB / 2; ++g) {
+            const uint32_t cur = (HALF + g) & 1u;
+            const bool copy = g + 1 < NB / 2 || res_next;
+            if (copy) stage_dma(g + 1 < NB / 2 ? HALF + g + 1 : 0u, cur ^ 1u);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (uint32_t jj = 0; jj < HALF; ++jj) av[jj] = la[jj * 64u];
+            for (uint32_t u = 0; u < 2; ++u) {
+                const uint32_t rb = 2u * g + u;
+                const f4 *la = (cur ? lds1 : lds0) + u * CF4 + (HALF * half) * 64u + lane;
+                f4 av[HALF];
 #pragma unroll
-            for (uint32_t e = 0; e < 4; ++e)
+                for (uint32_t jj = 0; jj < HALF; ++jj) av[jj] = la[jj * 64u];
 #pragma unroll
-                for (uint32_t jj = 0; jj < HALF; ++jj)
-                    gr[jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jj][e], acc[rb][e], gr[jj], 0, 0, 0);
+                for (uint32_t e = 0; e < 4; ++e)
+#pragma unroll
+                    for (uint32_t jj = 0; jj < HALF; ++jj)
+                        gr[jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[jj][e], acc[rb][e], gr[jj], 0, 0, 0);
+            }
+            if (copy) __builtin_amdgcn_s_waitcnt(0);  // this wave's copy has landed
+            __syncthreads();
         }
     };
 
@@ -188,9 +242,9 @@ __global__ __launch_bounds__(kGradBlock) void k_dense_grad(SwarmDev S, GradArgs 
         const float step = -2.0f * lr;  // p - lr * (2 A^T Y^T), one rounding
         // steps + 1 residuals: one per step, the last one scores the result.
         for (uint32_t k = 0;; ++k) {
-            residual();
+            residual(k < steps);
             if (k == steps) break;
-            gradient();
+            gradient(true);
 #pragma unroll
             for (uint32_t m = 0; m < HALF; ++m) {
                 const uint32_t j0 = 4u * (cbase + 4u * m + lg);
@@ -227,9 +281,9 @@ __global__ __launch_bounds__(kGradBlock) void k_dense_grad(SwarmDev S, GradArgs 
             wave_commit(S, t, blockIdx.x * 4u + grp4, key, 0u);
         }
     } else {
-        residual();
+        residual(MODE == MODE_GRAD);
         if constexpr (MODE == MODE_GRAD) {
-            gradient();
+            gradient(false);
             if (valid) {
                 const float scale = 2.0f * (G.gout ? G.gout[i] : 1.0f);
                 float *gr_out = G.g + (size_t)i * G.ld;
