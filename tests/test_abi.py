@@ -159,3 +159,15 @@ def test_batch_init_rejects_bad_arguments_before_touching_a_device():
                               ctypes.byref(b)) == binding.E_NOMEM
     assert b.value is None
     lib.sso_batch_destroy(None)
+
+
+def test_rocrand_cross_check_helper_loads():
+    """The tests' rocRAND helper (a second Philox4x32-10 for the GPU parity
+    tests) is built in-tree and exports its one entry point."""
+    import ctypes
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "rocrand_ref",
+                        "librocrand_philox.so")
+    assert os.path.exists(path), "build() compiles tests/rocrand_ref/librocrand_philox.so"
+    lib = ctypes.CDLL(path)
+    assert hasattr(lib, "rocrand_philox_blocks")

@@ -3,6 +3,8 @@
 Bit-exact positions, pBests, gBest indices and random words; FP32 fitness
 within 1e-5 relative of the oracle's FP64 value; decisions may differ only
 inside the near-tie band (see tests/parity.py)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -29,6 +31,35 @@ def test_device_words_match_oracle(n, d, t, swarm):
     pair = Pair("sphere", n, d, seed=0x1234_5678_9ABC_DEF0, swarm_id=swarm)
     got = pair.gpu.debug_rng(t)
     assert np.array_equal(got, oracle.words(0x1234_5678_9ABC_DEF0, swarm, t, n, d))
+
+
+ROCRAND_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "rocrand_ref",
+                           "librocrand_philox.so")
+
+
+@pytest.mark.parametrize("n,d,t,swarm,seed", [(300, 1000, 1, 0, 2), (64, 256, 4294967295, 7, 3),
+                                              (1000, 101, 77, 511, 0x1234_5678_9ABC_DEF0),
+                                              (5, 3, 0, 1, 2**64 - 1)])
+def test_device_words_match_rocrand(n, d, t, swarm, seed):
+    """A second implementation of Philox4x32-10: rocRAND's device generator
+    (run, not read; tests/rocrand_ref), with the counter (chunk, particle,
+    generation, swarm) mapped onto its (seed, subsequence, offset)."""
+    import ctypes
+
+    lib = ctypes.CDLL(ROCRAND_LIB)
+    lib.rocrand_philox_blocks.argtypes = [ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint32,
+                                          ctypes.c_void_p]
+    lib.rocrand_philox_blocks.restype = ctypes.c_int
+    pair = Pair("sphere", n, d, seed=seed, swarm_id=swarm)
+    got = pair.gpu.debug_rng(t)
+    chunks = (d + 3) // 4
+    q, i = np.meshgrid(np.arange(chunks, dtype=np.uint32), np.arange(n, dtype=np.uint32))
+    ctr = np.stack([q.ravel(), i.ravel(), np.full(q.size, t, np.uint32),
+                    np.full(q.size, swarm, np.uint32)], axis=1).astype(np.uint32)
+    out = np.zeros_like(ctr)
+    assert lib.rocrand_philox_blocks(seed, ctr.ctypes.data, ctr.shape[0], out.ctypes.data) == 0
+    ref = out.reshape(n, chunks * 4)[:, :d]
+    assert np.array_equal(got, ref)
 
 
 @pytest.mark.parametrize("n,d,offset", [(262150, 4, 0), (40, 1000, 0), (9, 8, 1), (33, 12, 2)])
