@@ -177,6 +177,23 @@ def test_batch_set_state_and_errors():
     assert e.value.code == E_INVAL
 
 
+@pytest.mark.parametrize("storage", ["auto", "f32"])
+def test_batch_largest_rows(storage):
+    """d = 1024, the largest a batched swarm takes, beside ragged and tiny
+    rows, under every mapping rule of the tuner."""
+    from paper_2110_01470_amd.binding import TUNE_CANDIDATES, Batch
+
+    shapes = [(2, 1024), (3, 1021), (70, 1024), (5, 2)]
+    swarms = make_swarms(shapes=shapes, storage=storage, seed=800)
+    batch = Batch(swarms)
+    batch.tune(1)
+    pairs = pairs_for(batch, swarms)
+    for pr in pairs:
+        pr.compare()
+    step_all(batch, pairs, 3)
+    assert len(TUNE_CANDIDATES) == 5
+
+
 def test_batch512_full_size_sampled():
     """The 512-swarm ripple batch at full size, as the benchmark launches it:
     init and two generations; eight swarms compared in full, every swarm's

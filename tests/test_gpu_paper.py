@@ -42,6 +42,15 @@ def test_cross_lane_functions_over_passes(kind, d, lanes):
     pair.step(8)
 
 
+@pytest.mark.parametrize("kind", ["f3", "f4", "f6", "f8", "f9"])
+@pytest.mark.parametrize("lanes", [8, 64])
+def test_largest_dimension(kind, lanes):
+    """d = 1024, the largest the Table 3.2 kernel takes (256 chunks staged)."""
+    pair = paper_pair(kind, n=6, d=1024, lanes=lanes, order=oracle.ORDER_GPS, seed=11)
+    pair.compare()
+    pair.step(4)
+
+
 @pytest.mark.parametrize("kind,d", [("f8", 3), ("f8", 7), ("f4", 1), ("f3", 1), ("f7", 1),
                                     ("f6", 2), ("f9", 5)])
 def test_small_and_ragged_dimensions(kind, d):

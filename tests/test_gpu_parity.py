@@ -144,6 +144,26 @@ def test_ripple_generations(n, d, order, storage):
     pair.step(25)
 
 
+@pytest.mark.parametrize("storage", ["u24", "f32"])
+@pytest.mark.parametrize("kind,n,d,order,lanes", [
+    ("ripple", 5, 1025, oracle.ORDER_GPS, 0),        # first size without LDS staging
+    ("ripple", 3, 5003, oracle.ORDER_EQ21, 0),       # many chunks per lane, ragged
+    ("ripple", 7, 2048, oracle.ORDER_GPS, 8),        # 64 chunks per lane
+    ("sphere", 2, 1 << 20, oracle.ORDER_GPS, 0),     # the largest d a swarm takes
+    ("sphere", 2, (1 << 20) - 3, oracle.ORDER_EQ21, 0),
+])
+def test_unstaged_and_largest_rows(kind, n, d, order, lanes, storage):
+    """Rows of more than 256 chunks: the shift, weights and gBest are read
+    from global memory instead of LDS, and each lane walks many chunks; up to
+    d = 2^20, the largest the library accepts."""
+    cg, cp, cw = (0.4, 0.7, 0.9) if order == oracle.ORDER_GPS else (0.8, 0.6, 0.3)
+    name = "ripple_n65536_d1000" if kind == "ripple" else "sphere_n100_d30"
+    pair = wl_pair(name, n=n, d=d, order=order, cg=cg, cp=cp, cw=cw, engine="stream",
+                   lanes=lanes, storage=storage)
+    pair.compare()
+    pair.step(3)
+
+
 @pytest.mark.parametrize("lanes", [8, 16, 32, 64])
 def test_sphere_u24_storage_mappings(lanes):
     pair = wl_pair("sphere_n100_d30", engine="stream", lanes=lanes, storage="u24")
