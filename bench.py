@@ -321,7 +321,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the swarm of one GPU is the unit; see the sharding notes in DESIGN.md)",
+              "(the benchmark measures one GPU's swarm; sharding over GPUs is not built)",
               file=sys.stderr)
         sys.exit(2)
 
