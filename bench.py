@@ -466,14 +466,24 @@ def bench_paper(pw, args):
     if args.cpu_gens is None or args.cpu_gens > 0:
         import oracle
 
-        orc = oracle.Swarm(pw.n, pw.d, oracle.F1 + int(pw.kind[1:]) - 1, pw.lo, pw.hi, pw.cg, pw.cp,
-                           pw.cw, pw.seed, None, order=oracle.ORDER_EQ21)
-        t0 = time.perf_counter()
-        orc.init()
-        orc.run(steps)
-        csec = time.perf_counter() - t0
-        cpu = {"value": csec, "unit": "s", "cores": 1, "kind": "oracle",
-               "sample": f"the whole {steps}-generation run of {pw.name}, single-threaded FP64 oracle"}
+        def whole_run(threads):
+            used = oracle.set_threads(threads)
+            try:
+                orc = oracle.Swarm(pw.n, pw.d, oracle.F1 + int(pw.kind[1:]) - 1, pw.lo, pw.hi,
+                                   pw.cg, pw.cp, pw.cw, pw.seed, None, order=oracle.ORDER_EQ21)
+                t0 = time.perf_counter()
+                orc.init()
+                orc.run(steps)
+                return time.perf_counter() - t0, used
+            finally:
+                oracle.set_threads(1)
+
+        csec1, _ = whole_run(1)
+        csec, used = whole_run(host_threads())
+        cpu = {"value": csec, "unit": "s", "cores": used, "kind": "oracle",
+               "sample": f"the whole {steps}-generation run of {pw.name}, FP64 oracle on {used} "
+                         f"threads; one thread: {csec1:.4f} s",
+               "single_thread": {"value": csec1, "cores": 1}}
     rec = {
         "metric": "wall time of a whole run (set-up, T generations, gBest to host)",
         "value": wall,
@@ -635,15 +645,27 @@ def cpu_polish_baseline(wl, lr, sample=1024):
     import oracle
 
     s, w, a = wl.objective()
-    orc = oracle.Swarm(sample, wl.d, oracle.DENSE, wl.lo, wl.hi, wl.cg, wl.cp, wl.cw, wl.seed, s,
-                       None, a)
-    orc.init()
-    t0 = time.perf_counter()
-    orc.polish(POLISH_STEPS, lr)
-    sec = time.perf_counter() - t0
-    return {"value": sample / sec, "unit": "pBests polished/s", "cores": 1, "kind": "oracle",
-            "sample": f"{POLISH_STEPS}-step polish of {sample} pBests of {wl.name}, single-threaded "
-                      f"FP64 oracle, {sec:.2f} s"}
+
+    def timed(threads, count):
+        used = oracle.set_threads(threads)
+        try:
+            orc = oracle.Swarm(count, wl.d, oracle.DENSE, wl.lo, wl.hi, wl.cg, wl.cp, wl.cw,
+                               wl.seed, s, None, a)
+            orc.init()
+            t0 = time.perf_counter()
+            orc.polish(POLISH_STEPS, lr)
+            return time.perf_counter() - t0, used
+        finally:
+            oracle.set_threads(1)
+
+    sec1, _ = timed(1, sample)
+    nth = host_threads()
+    many = sample * max(1, nth // 2)
+    sec, used = timed(nth, many)
+    return {"value": many / sec, "unit": "pBests polished/s", "cores": used, "kind": "oracle",
+            "sample": f"{POLISH_STEPS}-step polish of {many} pBests of {wl.name}, FP64 oracle on "
+                      f"{used} threads ({sec:.2f} s); one thread: {sample} pBests ({sec1:.2f} s)",
+            "single_thread": {"value": sample / sec1, "cores": 1}}
 
 
 def bench_batch(bw, args):

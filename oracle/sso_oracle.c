@@ -528,11 +528,14 @@ int orc_polish(orc_swarm *sw, uint32_t steps, double lr)
     if (sw->kind != ORC_DENSE) return -1;
     const uint32_t d = sw->d;
     const double lo = sw->rule.lo, hi = (double)(sw->rule.lo + sw->rule.span);
-    double *p = (double *)malloc(sizeof(double) * d);
-    double *g = (double *)malloc(sizeof(double) * d);
-    float *q = (float *)malloc(sizeof(float) * d);
     int replaced = 0;
+    /* Each pBest is polished on its own (scratch per particle), so the loop
+     * may run on several threads. */
+#pragma omp parallel for num_threads(g_threads) schedule(static) reduction(+ : replaced)
     for (uint32_t i = 0; i < sw->n; ++i) {
+        double *p = (double *)malloc(sizeof(double) * d);
+        double *g = (double *)malloc(sizeof(double) * d);
+        float *q = (float *)malloc(sizeof(float) * d);
         float *pi = sw->p + (size_t)i * d;
         for (uint32_t j = 0; j < d; ++j) q[j] = pi[j];
         for (uint32_t k = 0; k < steps; ++k) {
@@ -557,10 +560,10 @@ int orc_polish(orc_swarm *sw, uint32_t steps, double lr)
             sw->improved[i] = 1;
             ++replaced;
         }
+        free(q);
+        free(g);
+        free(p);
     }
     update_gbest(sw);
-    free(q);
-    free(g);
-    free(p);
     return replaced;
 }

@@ -238,6 +238,22 @@ def test_thread_count_does_not_change_results(kind):
             oracle.set_threads(1)
     for u, v in zip(*states):
         assert np.array_equal(u, v)
+    if kind == "dense":
+        # The polish runs its particles on several threads too.
+        polished = []
+        for threads in (1, 4):
+            oracle.set_threads(threads)
+            try:
+                sw, s, w, a = make_swarm(kind, n, d, 57)
+                sw.init().run(3)
+                sigma = np.linalg.norm(a.astype(np.float64), 2)
+                sw.polish(3, 0.05 / sigma**2)
+                polished.append((sw.p.copy(), sw.fp.copy(), sw.fx64.copy(), sw.improved.copy(),
+                                 sw.gidx))
+            finally:
+                oracle.set_threads(1)
+        for u, v in zip(*polished):
+            assert np.array_equal(u, v)
     w1 = oracle.words(3, 0, 5, 40, 9)
     oracle.set_threads(4)
     try:
