@@ -293,3 +293,35 @@ def test_trace_window_and_errors():
     assert e.value.code == E_STATE
     with pytest.raises(SSOError):
         pair.gpu.trace(18, 5)
+
+
+@pytest.mark.parametrize("engine", ["stream", "resident"])
+def test_zero_work_calls_change_nothing(engine):
+    """sso_run(0), an empty trace window and a batch run of 0 generations
+    leave every state as it was; the run continues in step with the oracle
+    afterwards."""
+    from paper_2110_01470_amd.binding import Batch
+
+    pair = wl_pair("sphere_n100_d30", n=37, d=30, engine=engine)
+    pair.step(3)
+    before = pair.gpu.state()
+    pair.gpu.run(0)
+    after = pair.gpu.state()
+    for u, v in zip(before[:3], after[:3]):
+        assert np.array_equal(u, v)
+    assert before[3] == after[3] == 3
+    fg, gi, im = pair.gpu.trace(1, 0)
+    assert fg.size == gi.size == im.size == 0
+    pair.step(2)
+
+    s = np.zeros(9, np.float32)
+    w = np.ones(9, np.float32)
+    batch = Batch([dict(n=20, d=9, kind="ripple", lo=-5.0, hi=5.0, cg=0.4, cp=0.7, cw=0.9,
+                        seed=3, s=s, w=w)])
+    batch.run(2)
+    b0 = batch.view(0).state()
+    batch.run(0)
+    b1 = batch.view(0).state()
+    for u, v in zip(b0[:3], b1[:3]):
+        assert np.array_equal(u, v)
+    assert batch.results()[3] == 2
