@@ -154,6 +154,10 @@ class Swarm:
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # The kernels use the workspace on self.stream: once the tensor is
+        # dropped, torch's allocator must not hand the memory out again before
+        # the work queued there has finished.
+        self.workspace.record_stream(self.stream)
         ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             rc = self._lib.sso_init(ctypes.byref(self._cfg), self.workspace.data_ptr(), nbytes,
@@ -316,6 +320,7 @@ class Batch:
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace.record_stream(self.stream)  # as for Swarm
         ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             rc = self._lib.sso_batch_init(arr, self.count, self.workspace.data_ptr(), nbytes,

@@ -325,3 +325,25 @@ def test_zero_work_calls_change_nothing(engine):
     for u, v in zip(b0[:3], b1[:3]):
         assert np.array_equal(u, v)
     assert batch.results()[3] == 2
+
+
+def test_dropping_a_swarm_with_queued_work_is_safe():
+    """A swarm dropped while its own stream still runs its generations: its
+    workspace must not be handed to the next allocation before that work
+    ends, so a swarm created right after (on the current stream) evolves
+    exactly as the oracle does."""
+    import torch
+
+    from paper_2110_01470_amd.binding import Swarm
+
+    wl = WORKLOADS["ripple_n65536_d1000"]
+    s, w, _ = wl.objective()
+    side = torch.cuda.Stream()
+    busy = Swarm(4096, wl.d, "ripple", wl.lo, wl.hi, wl.cg, wl.cp, wl.cw, wl.seed, s, w,
+                 engine="stream", stream=side)
+    busy.run(100)  # several milliseconds of work queued on `side`
+    del busy
+    pair = wl_pair("ripple_n65536_d1000", n=4096, d=wl.d, engine="stream")
+    pair.step(3)
+    side.synchronize()
+    pair.compare()
