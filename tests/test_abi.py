@@ -171,3 +171,26 @@ def test_rocrand_cross_check_helper_loads():
     assert os.path.exists(path), "build() compiles tests/rocrand_ref/librocrand_philox.so"
     lib = ctypes.CDLL(path)
     assert hasattr(lib, "rocrand_philox_blocks")
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/sso.h compiles as C99 (no C++ in the boundary), and a C
+    program that takes the address of every declared function links against
+    libsso.so."""
+    import subprocess
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    names = declared_functions()
+    src = tmp_path / "use_sso.c"
+    src.write_text('#include "sso.h"\n#include <stdio.h>\ntypedef void (*fn_t)(void);\n'
+                   'int main(void) {\n    fn_t fns[] = {\n'
+                   + "".join(f"        (fn_t)&{n},\n" for n in names)
+                   + "    };\n    printf(\"%d\\n\", (int)(sizeof fns / sizeof fns[0]));\n"
+                   "    return sso_strerror(SSO_OK)[0] == 'o' ? 0 : 1;\n}\n")
+    exe = tmp_path / "use_sso"
+    lib_dir = os.path.dirname(binding.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-pedantic", "-I",
+                    os.path.join(root, "include"), str(src), "-o", str(exe), "-L", lib_dir, "-lsso",
+                    f"-Wl,-rpath,{lib_dir}"], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    assert int(out) == len(names)
