@@ -230,3 +230,15 @@ def pairs_for_one(batch, swarms, k):
     return Pair(sw["kind"], sw["n"], sw["d"], lo=sw["lo"], hi=sw["hi"], cg=sw["cg"], cp=sw["cp"],
                 cw=sw["cw"], seed=sw["seed"], swarm_id=sw["swarm_id"],
                 objective=(sw["s"], sw["w"], None), gpu=batch.view(k))
+
+
+def test_tune_after_generations_is_refused():
+    from paper_2110_01470_amd.binding import E_STATE, Batch, SSOError
+
+    swarms = make_swarms(shapes=[(20, 9), (7, 30)], seed=41)
+    batch = Batch(swarms)
+    batch.run(2)
+    with pytest.raises(SSOError) as e:
+        batch.tune(1)
+    assert e.value.code == E_STATE
+    assert batch.results()[3] == 2  # the batch is left as it was

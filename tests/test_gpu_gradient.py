@@ -269,3 +269,22 @@ def test_polish_full_size_sampled():
     g, fg, gidx, _ = sw.best()
     assert fg == fp1.min() and gidx == int(np.argmin(fp1)) and np.array_equal(g, p1[gidx])
     assert np.all(fp1 <= fp0)
+
+
+def test_eval_and_rng_argument_errors():
+    """sso_eval on a separable swarm, and a word request for a generation
+    beyond 32 bits, are refused with their codes; nothing is launched."""
+    import torch
+
+    from paper_2110_01470_amd.binding import E_INVAL, E_UNSUPPORTED, SSOError, Swarm
+
+    s1, w1, _ = make_objective("ripple", 8, 1, -1.0, 1.0)
+    rip = Swarm(10, 8, "ripple", -2.0, 2.0, 0.4, 0.7, 0.9, 1, s1, w1)
+    with pytest.raises(SSOError) as e:
+        rip.eval(torch.zeros(4, 8, device="cuda"), f=True)
+    assert e.value.code == E_UNSUPPORTED
+    with pytest.raises(SSOError) as e:
+        rip.debug_rng(1 << 32)
+    assert e.value.code == E_INVAL
+    rip.run(2)
+    assert rip.best()[3] == 2
