@@ -57,11 +57,9 @@ __global__ void k_batch_collect(BatchDev B, uint32_t t)
     const bool used = lane < S.nsub;
     unsigned long long k = used ? *sub_key(S, g, lane) : ~0ull;
     uint32_t c = used ? *sub_cnt(S, g, lane) : 0u;
+    k = wave_min_u64(k);
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        k = min_u64(k, shfl_xor_u64(k, m));
-        c += __shfl_xor(c, m, 64);
-    }
+    for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m, 64);
     if (lane == 0) {
         B.results[2u * blockIdx.x] = k;
         B.results[2u * blockIdx.x + 1u] = c;

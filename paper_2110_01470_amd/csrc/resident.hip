@@ -81,11 +81,9 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, ui
             const uint32_t g = (t_first - 1u) % kGroups;
             unsigned long long k = *sub_key(S, g, lane);
             uint32_t cc = *sub_cnt(S, g, lane);
+            k = wave_min_u64(k);
 #pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) {
-                k = min_u64(k, shfl_xor_u64(k, m));
-                cc += __shfl_xor(cc, m, 64);
-            }
+            for (int m = 32; m >= 1; m >>= 1) cc += __shfl_xor(cc, m, 64);
             if (lane == 0) {
                 s_first = k;
                 S.keys[(t_first - 1u) % S.trace_cap] = k;
@@ -118,8 +116,14 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, ui
             fp = acc;
         }
         unsigned long long key = valid ? gbest_key(fp, i, 0u) : ~0ull;
+        // Keys are equal within a particle's lanes, so the masks from L up
+        // suffice; a few permutes are cheaper here than the full DPP minimum.
 #pragma unroll
-        for (int m = 32; m >= L; m >>= 1) key = min_u64(key, shfl_xor_u64(key, m));
+        for (int m = 32; m >= L; m >>= 1) {
+            const uint32_t lo = __shfl_xor((uint32_t)key, m, 64);
+            const uint32_t hi = __shfl_xor((uint32_t)(key >> 32), m, 64);
+            key = min_u64(key, ((unsigned long long)hi << 32) | lo);
+        }
         const uint32_t cnt = (uint32_t)__popcll(__ballot(improved && c == 0));
         if (lane == 0) {
             s_key[wave] = key;

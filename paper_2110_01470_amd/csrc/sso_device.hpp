@@ -366,16 +366,42 @@ __device__ __forceinline__ unsigned long long gbest_key(float f, uint32_t i, uin
     return ((unsigned long long)orderable(f) << 32) | ((unsigned long long)i << 1) | row;
 }
 
-__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m)
-{
-    const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
-    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
 __device__ __forceinline__ unsigned long long min_u64(unsigned long long a, unsigned long long b)
 {
     return a < b ? a : b;
+}
+
+// min(x, x of the lane the DPP control CTRL names), both halves moved by the
+// same row-local pattern.  A lane whose source is off keeps its own value.
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_min_u64(unsigned long long x)
+{
+    const int lo = (int)(uint32_t)x, hi = (int)(uint32_t)(x >> 32);
+    const uint32_t plo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    const uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    return min_u64(x, ((unsigned long long)phi << 32) | plo);
+}
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Minimum of x over the 64 lanes of the wave, the same value in every lane;
+// called with every lane of the wave active.  A minimum does not depend on
+// the order it is taken in, so this is the shuffle butterfly's result with
+// row-local DPP moves (pairs, quads, half rows, rows of 16) instead of LDS
+// permutes, and the four row minima read out as wave-uniform values.
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x)
+{
+    x = dpp_min_u64<0xB1>(x);   // quad_perm(1, 0, 3, 2)
+    x = dpp_min_u64<0x4E>(x);   // quad_perm(2, 3, 0, 1)
+    x = dpp_min_u64<0x141>(x);  // row_half_mirror
+    x = dpp_min_u64<0x140>(x);  // row_mirror
+    return min_u64(min_u64(readlane_u64(x, 0), readlane_u64(x, 16)),
+                   min_u64(readlane_u64(x, 32), readlane_u64(x, 48)));
 }
 
 __device__ __forceinline__ unsigned long long *sub_key(const SwarmDev &S, uint32_t group,
@@ -415,8 +441,7 @@ __device__ __forceinline__ unsigned long long generation_begin(const SwarmDev &S
     if (threadIdx.x < 64u) {
         const uint32_t g = (t - 1u) % kGroups;
         const bool used = lane < S.nsub;
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) k = min_u64(k, shfl_xor_u64(k, m));
+        k = wave_min_u64(k);
         if (lane == 0) s_best = k;
         if (blk == 0) {
             uint32_t c = used ? *sub_cnt(S, g, lane) : 0u;
@@ -448,8 +473,7 @@ __device__ __forceinline__ unsigned long long generation_begin(const SwarmDev &S
 __device__ __forceinline__ void wave_commit(const SwarmDev &S, uint32_t t, uint32_t wave_id,
                                             unsigned long long key, uint32_t improved)
 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) key = min_u64(key, shfl_xor_u64(key, m));
+    key = wave_min_u64(key);
     const uint32_t cnt = (uint32_t)__popcll(__ballot(improved != 0u));
     if ((threadIdx.x & 63u) == 0u) {
         const uint32_t g = t % kGroups, j = wave_id & (S.nsub - 1u);
@@ -468,8 +492,7 @@ __device__ __forceinline__ void generation_commit(const SwarmDev &S, uint32_t t,
     __shared__ unsigned long long s_key[NW];
     __shared__ uint32_t s_cnt[NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) key = min_u64(key, shfl_xor_u64(key, m));
+    key = wave_min_u64(key);
     const uint32_t cnt = (uint32_t)__popcll(__ballot(improved != 0u));
     if (lane == 0) {
         s_key[wave] = key;
