@@ -18,6 +18,17 @@ namespace sso {
 // generation, swarm), so generation and swarm are wave-uniform and the first
 // round's second product is a scalar multiply.
 // ---------------------------------------------------------------------------
+
+// a ^ b ^ k in one VALU instruction (gfx950's three-input bitwise op; 0x96 is
+// the truth table of the three-way parity, whatever the operand order).  k
+// must be wave-uniform: it is read from a scalar register.
+__device__ __forceinline__ uint32_t xor3_vvs(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -28,8 +39,16 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
         }
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
-                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        if (r < 2) {
+            // Rounds 1 and 2 xor wave-uniform words (generation, swarm, the
+            // low half of a uniform product), which the compiler folds into
+            // the key with scalar instructions.
+            c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                           (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        } else {
+            c = make_uint4(xor3_vvs((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                           xor3_vvs((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
+        }
     }
     return c;
 }
