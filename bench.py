@@ -35,6 +35,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP32_MATRIX_PEAK_TFLOPS = 157.3
+BF16_MATRIX_PEAK_TFLOPS = 2500.0  # dense, no sparsity
 BYTES_PER_UPDATE = 12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # Sources each workload's generation kernel is compiled from: a committed
@@ -73,7 +74,7 @@ def measured_traffic(wl):
     return rec.get("bytes_per_launch")
 
 
-def time_gpu(wl, steps, warmup, engine):
+def time_gpu(wl, steps, warmup, engine, contraction="auto"):
     import torch
 
     from paper_2110_01470_amd.binding import Swarm
@@ -82,12 +83,12 @@ def time_gpu(wl, steps, warmup, engine):
     stream = torch.cuda.Stream()
     args = (wl.n, wl.d, wl.kind, wl.lo, wl.hi, wl.cg, wl.cp, wl.cw, wl.seed, s, w, a)
     if warmup:
-        warm = Swarm(*args, engine=engine, stream=stream)
+        warm = Swarm(*args, engine=engine, contraction=contraction, stream=stream)
         warm.run(warmup)
         stream.synchronize()
         warm.close()
         del warm
-    sw = Swarm(*args, engine=engine, stream=stream)
+    sw = Swarm(*args, engine=engine, contraction=contraction, stream=stream)
     stream.synchronize()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -304,6 +305,8 @@ def main():
     ap.add_argument("--tune-gens", type=int, default=5,
                     help="generations the batch mapping tuner times per candidate")
     ap.add_argument("--engine", default="auto", choices=["auto", "stream", "resident"])
+    ap.add_argument("--contraction", default="auto", choices=["auto", "f32", "bf16x3"],
+                    help="dense objective: FP32 or split-bf16 matrix cores")
     ap.add_argument("--cpu-gens", type=int, default=None,
                     help="oracle generations for cpu_baseline (0 = skip)")
     ap.add_argument("--ceilings", action="store_true",
@@ -341,14 +344,22 @@ def main():
         return
     steps = args.steps if args.steps is not None else wl.generations
     log(f"workload {wl.name}: N={wl.n} D={wl.d} steps={steps} warmup={args.warmup}")
-    ms, fg, gen = time_gpu(wl, steps, args.warmup, args.engine)
+    ms, fg, gen = time_gpu(wl, steps, args.warmup, args.engine, args.contraction)
     sec = ms / 1e3
     updates = wl.n * wl.d * steps
     value = updates / sec
     ms_per_step = ms / steps
     log(f"gpu: {ms:.3f} ms for {steps} generations, fG={fg:.6g} at t={gen}")
 
-    if wl.kind == "dense":
+    split = wl.kind == "dense" and args.contraction == "bf16x3"
+    if split:
+        # The split contraction runs six bf16 products per FP32 product on the
+        # bf16 matrix cores: priced at their work and their peak.
+        flop = 6 * 2.0 * wl.n * wl.d * wl.d
+        achieved = flop / (ms_per_step / 1e3) / 1e12
+        roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_MATRIX_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / BF16_MATRIX_PEAK_TFLOPS, "traffic": None}
+    elif wl.kind == "dense":
         flop = 2.0 * wl.n * wl.d * wl.d
         achieved = flop / (ms_per_step / 1e3) / 1e12
         roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MATRIX_PEAK_TFLOPS,
@@ -393,10 +404,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16x3" if split else "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "objective": wl.kind, "n": wl.n, "d": wl.d,
-                   "generations": steps, "engine": args.engine},
+                   "generations": steps, "engine": args.engine,
+                   **({"contraction": args.contraction} if wl.kind == "dense" else {})},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

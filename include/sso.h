@@ -96,6 +96,14 @@ typedef enum {
  * only positions on that grid. */
 typedef enum { SSO_STORAGE_AUTO = 0, SSO_STORAGE_F32 = 1, SSO_STORAGE_U24 = 2 } sso_storage;
 
+/* DENSE objective: how the generation kernel forms A (x - s).
+ * F32: on FP32 matrix cores (v_mfma_f32_16x16x4_f32).
+ * BF16X3: every FP32 operand is split exactly into three bf16 parts and the
+ * six part products above 2^-24 relative weight go through bf16 matrix
+ * cores with FP32 accumulation (the three omitted are below 2^-23 |a d|);
+ * the device holds a second copy of A, 6 dp^2 bytes.  AUTO = F32. */
+typedef enum { SSO_CONTRACT_AUTO = 0, SSO_CONTRACT_F32 = 1, SSO_CONTRACT_BF16X3 = 2 } sso_contraction;
+
 typedef struct {
     uint32_t n;          /* Nsol, particles, >= 1, < 2^31                         */
     uint32_t d;          /* Nvar, variables per particle, >= 1 (DENSE: <= 256)    */
@@ -121,6 +129,7 @@ typedef struct {
                               sso_polish(polish_steps, polish_lr)               */
     uint32_t polish_steps; /* gradient steps per polish (used when polish_every) */
     float    polish_lr;    /* step size; <= 0 means 0.05 / sigma_max(A)^2        */
+    int32_t  contraction;  /* sso_contraction (DENSE only; ignored otherwise)    */
 } sso_config;
 
 typedef struct sso_ctx sso_ctx;

@@ -20,6 +20,7 @@ OBJ = {"sphere": 0, "ripple": 1, "dense": 2, "f1": 11, "f2": 12, "f3": 13, "f4":
 ORDER_GPS, ORDER_EQ21 = 0, 1
 ENGINE = {"auto": 0, "stream": 1, "resident": 2}
 STORAGE = {"auto": 0, "f32": 1, "u24": 2}
+CONTRACTION = {"auto": 0, "f32": 1, "bf16x3": 2}
 
 
 class SSOError(RuntimeError):
@@ -52,6 +53,7 @@ class Config(ctypes.Structure):
         ("polish_every", ctypes.c_uint32),
         ("polish_steps", ctypes.c_uint32),
         ("polish_lr", ctypes.c_float),
+        ("contraction", ctypes.c_int32),
     ]
 
 
@@ -114,7 +116,7 @@ def _f32(a):
 
 def make_config(n, d, kind, lo, hi, cg, cp, cw, seed, s, w=None, a=None, swarm_id=0,
                 order=ORDER_GPS, engine="auto", lanes=0, trace_cap=0, storage="auto",
-                polish_every=0, polish_steps=0, polish_lr=0.0):
+                polish_every=0, polish_steps=0, polish_lr=0.0, contraction="auto"):
     """Returns (Config, keepalive) with host arrays pinned in `keepalive`."""
     s, w, a = _f32(s), _f32(w), _f32(a)
     cfg = Config(n=n, d=d, lo=lo, hi=hi, cg=cg, cp=cp, cw=cw, seed=seed, swarm_id=swarm_id,
@@ -124,7 +126,8 @@ def make_config(n, d, kind, lo, hi, cg, cp, cw, seed, s, w=None, a=None, swarm_i
                  trace_cap=trace_cap, s=s.ctypes.data if s is not None else None,
                  w=w.ctypes.data if w is not None else None,
                  a=a.ctypes.data if a is not None else None, polish_every=polish_every,
-                 polish_steps=polish_steps, polish_lr=polish_lr)
+                 polish_steps=polish_steps, polish_lr=polish_lr,
+                 contraction=CONTRACTION[contraction] if isinstance(contraction, str) else contraction)
     return cfg, (s, w, a)
 
 
@@ -142,14 +145,15 @@ class Swarm:
 
     def __init__(self, n, d, kind, lo, hi, cg, cp, cw, seed, s, w=None, a=None, swarm_id=0,
                  order=ORDER_GPS, engine="auto", lanes=0, trace_cap=0, storage="auto",
-                 polish_every=0, polish_steps=0, polish_lr=0.0, device="cuda", stream=None):
+                 polish_every=0, polish_steps=0, polish_lr=0.0, contraction="auto",
+                 device="cuda", stream=None):
         import torch
 
         self._lib = load()
         self.n, self.d = n, d
         self._cfg, self._keep = make_config(n, d, kind, lo, hi, cg, cp, cw, seed, s, w, a,
                                             swarm_id, order, engine, lanes, trace_cap, storage,
-                                            polish_every, polish_steps, polish_lr)
+                                            polish_every, polish_steps, polish_lr, contraction)
         nbytes = workspace_bytes(self._cfg)
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

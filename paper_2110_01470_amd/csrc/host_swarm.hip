@@ -145,6 +145,7 @@ int validate(const sso_config *c, std::string *why)
         return bad(SSO_E_UNSUPPORTED, "the gradient polish needs the dense objective");
     if (!(c->polish_lr == c->polish_lr) || std::isinf(c->polish_lr)) return bad(SSO_E_INVAL, "polish_lr must be finite");
     if (c->storage < SSO_STORAGE_AUTO || c->storage > SSO_STORAGE_U24) return bad(SSO_E_INVAL, "unknown storage");
+    if (c->contraction < SSO_CONTRACT_AUTO || c->contraction > SSO_CONTRACT_BF16X3) return bad(SSO_E_INVAL, "unknown contraction");
     if (c->storage == SSO_STORAGE_U24) {
         int e, st;
         resolve(*c, &e, &st);

@@ -38,10 +38,16 @@ using namespace sso::host;
 thread_local std::string g_err;
 
 struct Layout {
-    size_t rows, fp, st, s, w, a, at, keys, cnt, sub, total;
+    size_t rows, fp, st, s, w, a, at, a3, keys, cnt, sub, total;
     uint32_t dp, stride, trace_cap;
     int engine, storage;
 };
+
+// The DENSE generation kernel takes the split bf16 contraction.
+bool split_contraction(const sso_config &c)
+{
+    return c.kind == SSO_OBJ_DENSE && c.contraction == SSO_CONTRACT_BF16X3;
+}
 
 Layout make_layout(const sso_config &c)
 {
@@ -58,6 +64,7 @@ Layout make_layout(const sso_config &c)
     L.w = off;    off += c.kind == SSO_OBJ_RIPPLE ? align256((size_t)L.dp * sizeof(float)) : 0;
     L.a = off;    off += c.kind == SSO_OBJ_DENSE ? align256(dense_matrix_floats(c.d) * sizeof(float)) : 0;
     L.at = off;   off += c.kind == SSO_OBJ_DENSE ? align256(dense_matrix_floats(c.d) * sizeof(float)) : 0;
+    L.a3 = off;   off += split_contraction(c) ? align256(dense_split_halves(c.d) * sizeof(uint16_t)) : 0;
     L.keys = off; off += align256((size_t)L.trace_cap * sizeof(unsigned long long));
     L.cnt = off;  off += align256((size_t)L.trace_cap * sizeof(uint32_t));
     L.sub = off;  off += align256((size_t)kSubWords * sizeof(unsigned long long));
@@ -220,6 +227,7 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
     S.w = cfg->kind == SSO_OBJ_RIPPLE ? (const float *)(base + L.w) : nullptr;
     S.a = cfg->kind == SSO_OBJ_DENSE ? (const float *)(base + L.a) : nullptr;
     S.at = cfg->kind == SSO_OBJ_DENSE ? (const float *)(base + L.at) : nullptr;
+    S.a3 = split_contraction(*cfg) ? (const uint16_t *)(base + L.a3) : nullptr;
     S.keys = (unsigned long long *)(base + L.keys);
     S.cnt = (uint32_t *)(base + L.cnt);
     S.sub = (unsigned long long *)(base + L.sub);
@@ -243,6 +251,7 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
     rc = upload_separable(*cfg, S, ctx->stream, err);
     if (rc != SSO_OK) return fail(rc);
     std::vector<float> apack, atpack;
+    std::vector<uint16_t> a3pack;
     if (cfg->kind == SSO_OBJ_DENSE) {
         const uint32_t d = cfg->d;
         ctx->a_host.assign(cfg->a, cfg->a + (size_t)d * d);
@@ -258,6 +267,12 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
         if (e == hipSuccess)
             e = hipMemcpyAsync((void *)S.at, atpack.data(), sizeof(float) * atpack.size(),
                                hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess && S.a3) {
+            a3pack.assign(dense_split_halves(d), 0);
+            dense_pack_split(cfg->a, d, a3pack.data());
+            e = hipMemcpyAsync((void *)S.a3, a3pack.data(), sizeof(uint16_t) * a3pack.size(),
+                               hipMemcpyHostToDevice, ctx->stream);
+        }
         if (e != hipSuccess) return fail(hip_fail(err, e, "upload a"));
         ctx->polish_every = cfg->polish_every;
         ctx->polish_steps = cfg->polish_steps;

@@ -64,6 +64,7 @@ struct SwarmDev {
     const float *w;              // [dp] ripple weights, zero padded (or null)
     const float *a;              // dense matrix, layout of the dense kernel (or null)
     const float *at;             // its transpose in the same layout (dense only)
+    const uint16_t *a3;          // dense matrix split into three bf16 parts (split contraction), or null
     unsigned long long *keys;    // [trace_cap] gBest key per finished generation (ring)
     uint32_t *cnt;               // [trace_cap] improved pBests per finished generation (ring)
     unsigned long long *sub;     // [kGroups][kSubSlots][kSubStride]: key, then count
@@ -104,6 +105,7 @@ int launch_debug_rng(const SwarmDev &S, uint32_t t, uint32_t *out, void *stream)
 int launch_resident(const SwarmDev &S, uint32_t t_first, uint32_t generations, void *stream);
 bool resident_fits(uint32_t n, uint32_t d, int kind);
 uint64_t dense_matrix_floats(uint32_t d);
+uint64_t dense_split_halves(uint32_t d);  // bf16 values of the split matrix
 
 int launch_batch_fill(const BatchDev &B, void *stream);    // every swarm's trace ring and sub-slots
 int launch_batch_init(const BatchDev &B, void *stream);    // generation 0 of every swarm
@@ -116,6 +118,7 @@ int batch_graph(const BatchDev &B, uint32_t k, void **graph_out);
 int launch_batch_collect(const BatchDev &B, uint32_t t, void *stream);
 size_t batch_stage_bytes(int kind, int storage, uint32_t chunks);
 void dense_pack_matrix(const float *a, uint32_t d, float *out);
+void dense_pack_split(const float *a, uint32_t d, uint16_t *out);
 
 // Dense objective at given points and its gradient (grad_dense.hip).
 struct GradArgs {

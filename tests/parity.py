@@ -39,7 +39,8 @@ class Pair:
 
     def __init__(self, kind, n, d, lo=-100.0, hi=100.0, cg=0.4, cp=0.7, cw=0.9, seed=1,
                  s_range=(-50.0, 50.0), order=oracle.ORDER_GPS, engine="auto", lanes=0,
-                 swarm_id=0, trace_cap=0, storage="auto", objective=None, gpu=None):
+                 swarm_id=0, trace_cap=0, storage="auto", objective=None, gpu=None,
+                 contraction="auto"):
         """`objective` = (s, w, a) overrides the seeded instance; `gpu` is an
         already built GPU side (a swarm of a batch) instead of a new Swarm."""
         from paper_2110_01470_amd.binding import Swarm
@@ -54,7 +55,7 @@ class Pair:
         if gpu is None:
             gpu = Swarm(n, d, kind, lo, hi, cg, cp, cw, seed, self.s, self.w, self.a,
                         swarm_id=swarm_id, order=order, engine=engine, lanes=lanes,
-                        trace_cap=trace_cap, storage=storage)
+                        trace_cap=trace_cap, storage=storage, contraction=contraction)
         self.gpu = gpu
         self.orc.init()
         self.band_events = 0

@@ -59,6 +59,24 @@ def test_workspace_bytes_for_valid_configs():
     assert binding.workspace_bytes(c) >= 2 * 16384 * 256 * 4 + 256 * 256 * 4
 
 
+@pytest.mark.parametrize("d", [256, 100, 1])
+def test_split_contraction_adds_the_bf16_parts_of_a(d):
+    """The split contraction keeps A's three bf16 parts beside the FP32
+    copies: 3 x dp^2 halves, dp = d rounded up to 32 (256-byte aligned)."""
+    a = np.eye(d, dtype=np.float32)
+    c32, k1 = cfg(n=1000, d=d, kind="dense", a=a, contraction="f32")
+    c3, k2 = cfg(n=1000, d=d, kind="dense", a=a, contraction="bf16x3")
+    ca, k3 = cfg(n=1000, d=d, kind="dense", a=a)
+    dp = (d + 31) // 32 * 32
+    extra = (3 * dp * dp * 2 + 255) // 256 * 256
+    assert binding.workspace_bytes(c3) - binding.workspace_bytes(c32) == extra
+    assert binding.workspace_bytes(ca) == binding.workspace_bytes(c32)
+    # Separable objectives ignore the field.
+    cs, k4 = cfg(n=1000, d=d, contraction="bf16x3")
+    cf, k5 = cfg(n=1000, d=d, contraction="f32")
+    assert binding.workspace_bytes(cs) == binding.workspace_bytes(cf)
+
+
 @pytest.mark.parametrize("kw", [
     dict(n=0), dict(d=0), dict(lo=1.0, hi=1.0), dict(lo=float("nan")),
     dict(cg=0.8), dict(cp=0.95), dict(cw=1.0 - 2.0 ** -8), dict(cw=1.5),
@@ -70,6 +88,7 @@ def test_workspace_bytes_for_valid_configs():
     dict(polish_every=50, polish_steps=5), dict(kind="ripple", w=np.ones(30, np.float32), polish_every=1),
     dict(kind="dense", a=np.eye(30, dtype=np.float32), polish_lr=float("nan")),
     dict(storage="u24", kind="dense", a=np.eye(30, dtype=np.float32)),
+    dict(contraction=3), dict(contraction=-1),
 ])
 def test_invalid_configs_are_rejected(kw):
     c, keep = cfg(**kw)

@@ -1,0 +1,63 @@
+"""The dense objective's split bf16 contraction (contraction="bf16x3")
+against the CPU oracle, through the C ABI: the same bar as the FP32
+contraction -- bit-exact positions, pBests and gBest indices, FP32 fitness
+within 1e-5 relative of the oracle's FP64 value, decisions apart only inside
+the near-tie band."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_01470_amd.inputs import WORKLOADS
+from parity import Pair
+
+pytestmark = pytest.mark.gpu
+
+
+def split_pair(n, d, **over):
+    wl = WORKLOADS["dense_n16384_d256"]
+    kw = dict(lo=wl.lo, hi=wl.hi, cg=wl.cg, cp=wl.cp, cw=wl.cw, seed=wl.seed,
+              s_range=(wl.s_lo, wl.s_hi), contraction="bf16x3")
+    kw.update(over)
+    return Pair("dense", n, d, **kw)
+
+
+@pytest.mark.parametrize("n,d", [(130, 256), (70, 100), (3, 1), (64, 32)])
+def test_split_initialisation(n, d):
+    pair = split_pair(n, d, lo=-10.0, hi=10.0, s_range=(-5.0, 5.0), seed=11)
+    pair.compare()
+    fg, gi, im = pair.gpu.trace(0, 1)
+    assert gi[0] == pair.orc.gidx and im[0] == n
+
+
+@pytest.mark.parametrize("n,d,order", [(130, 256, oracle.ORDER_GPS), (64, 256, oracle.ORDER_EQ21),
+                                       (70, 100, oracle.ORDER_GPS), (100, 30, oracle.ORDER_GPS),
+                                       (65, 255, oracle.ORDER_GPS), (17, 1, oracle.ORDER_GPS),
+                                       (200, 64, oracle.ORDER_GPS), (129, 160, oracle.ORDER_EQ21)])
+def test_split_generations(n, d, order):
+    cg, cp, cw = (0.4, 0.7, 0.9) if order == oracle.ORDER_GPS else (0.8, 0.6, 0.3)
+    pair = split_pair(n, d, order=order, cg=cg, cp=cp, cw=cw)
+    pair.step(20)
+
+
+def test_split_full_size():
+    """The dense workload at full size (N=16384, D=256) with the split
+    contraction, as the benchmark launches it."""
+    pair = split_pair(16384, 256)
+    pair.compare()
+    pair.step(2)
+
+
+def test_split_and_f32_contractions_take_the_same_path():
+    """Both contractions from one instance: identical positions and pBests
+    over 30 generations unless a decision falls in the near-tie band, and
+    fitness values within the tolerance of each other."""
+    a = split_pair(96, 256, contraction="f32")
+    b = split_pair(96, 256)
+    a.gpu.run(30)
+    b.gpu.run(30)
+    xa, pa, fa, ta = a.gpu.state()
+    xb, pb, fb, tb = b.gpu.state()
+    assert ta == tb == 30
+    if np.array_equal(pa, pb):
+        assert np.array_equal(xa, xb)
+        np.testing.assert_allclose(fb, fa, rtol=2e-5)
