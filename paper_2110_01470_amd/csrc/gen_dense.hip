@@ -298,9 +298,9 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
 // so step m is one contiguous 3 x NB KB block, double-buffered in LDS.
 //
 // Pipeline: during step m's MFMAs the wave selects step m + 1's variables
-// (Philox, Eq. 2.1, the split), woven between the MFMAs so that VALU work
-// issues while the matrix cores run; step m + 1's A block and step m + 2's
-// row operands are requested at the start of step m.  With d = dp the
+// (Philox, Eq. 2.1, the split), in the same scheduling region, so that VALU
+// work issues while the matrix cores run; step m + 1's A block and step
+// m + 2's row operands are requested at the start of step m.  With d = dp the
 // select has no branch (see `ie`) and the end of a step waits only for the
 // A block, then meets the other waves at a bare barrier (they share nothing
 // but LDS); other shapes take the plain wait and __syncthreads.
@@ -521,10 +521,10 @@ __global__ __launch_bounds__(256) void k_dense3(SwarmDev S, uint32_t t)
     __builtin_amdgcn_s_waitcnt(0);  // buffer 0 and step 1's operands have landed
     __syncthreads();
 
-    // Step m: the MFMAs of step m (operands selected one step earlier) with
-    // the select of step m + 1 woven between them, so that the VALU work
-    // issues while the matrix cores run; step m + 1's A block and step
-    // m + 2's operands are requested first.
+    // Step m: the MFMAs of step m (operands selected one step earlier) and
+    // the select of step m + 1 in one region, so that the VALU work issues
+    // while the matrix cores run; step m + 1's A block and step m + 2's
+    // operands are requested first.
 #pragma unroll
     for (uint32_t m = 0; m < STEPS; ++m) {
         const uint32_t cur = m & 1u;
@@ -569,14 +569,9 @@ __global__ __launch_bounds__(256) void k_dense3(SwarmDev S, uint32_t t)
                 acc[r0 + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[q], dh, acc[r0 + q], 0, 0, 0);
         }
         if (more) {
-            // Weave: per MFMA two VALU instructions, and one LDS read every
-            // other MFMA (the A operands of the next row blocks).
-#pragma unroll
-            for (uint32_t k = 0; k < 6u * NB; ++k) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-                __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // VALU
-                if (k & 1u) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
-            }
+            // The select and the MFMAs share one branch-free region, which
+            // the compiler's scheduler interleaves by itself (fixed patterns
+            // of MFMA, VALU and LDS-read groups measured slower).
             if constexpr (FULL_D && !INIT) {
                 // Step m + 1's A block has landed once at most the eight
                 // operand loads of step m + 2 (issued after the copy) are
