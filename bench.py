@@ -351,14 +351,17 @@ def main():
     ms_per_step = ms / steps
     log(f"gpu: {ms:.3f} ms for {steps} generations, fG={fg:.6g} at t={gen}")
 
-    split = wl.kind == "dense" and args.contraction == "bf16x3"
+    split = wl.kind == "dense" and args.contraction != "f32"
     if split:
         # The split contraction runs six bf16 products per FP32 product on the
-        # bf16 matrix cores: priced at their work and their peak.
+        # bf16 matrix cores: priced at their work and their peak.  The
+        # FP32-equivalent rate against the FP32 matrix peak is given beside it.
         flop = 6 * 2.0 * wl.n * wl.d * wl.d
         achieved = flop / (ms_per_step / 1e3) / 1e12
+        fp32_eq = achieved / 6 / FP32_MATRIX_PEAK_TFLOPS
         roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_MATRIX_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / BF16_MATRIX_PEAK_TFLOPS, "traffic": None}
+                    "unit": "TFLOP/s", "frac": achieved / BF16_MATRIX_PEAK_TFLOPS, "traffic": None,
+                    "fp32_equivalent_frac": fp32_eq}
     elif wl.kind == "dense":
         flop = 2.0 * wl.n * wl.d * wl.d
         achieved = flop / (ms_per_step / 1e3) / 1e12
@@ -408,7 +411,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "objective": wl.kind, "n": wl.n, "d": wl.d,
                    "generations": steps, "engine": args.engine,
-                   **({"contraction": args.contraction} if wl.kind == "dense" else {})},
+                   **({"contraction": "f32" if args.contraction == "f32" else "bf16x3"}
+                      if wl.kind == "dense" else {})},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -576,7 +580,7 @@ def bench_polish(wl, args):
     runs = {}
     for name, kw in (("plain", {}), ("polished", dict(polish_every=POLISH_EVERY,
                                                        polish_steps=POLISH_STEPS))):
-        sw = Swarm(*args_, stream=stream, trace_cap=steps + 8, **kw)
+        sw = Swarm(*args_, stream=stream, trace_cap=steps + 8, contraction=args.contraction, **kw)
         stream.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -589,7 +593,7 @@ def bench_polish(wl, args):
         log(f"{name}: {ms:.1f} ms for {steps} generations, final fG {fg[-1]:.6g}")
         sw.close()
     # The polish kernel alone: (4 steps + 2) N D^2 FLOP per call.
-    sw = Swarm(*args_, stream=stream)
+    sw = Swarm(*args_, stream=stream, contraction=args.contraction)
     sw.run(10)
     lr = sw.polish(POLISH_STEPS)
     reps = 20

@@ -101,7 +101,7 @@ typedef enum { SSO_STORAGE_AUTO = 0, SSO_STORAGE_F32 = 1, SSO_STORAGE_U24 = 2 } 
  * BF16X3: every FP32 operand is split exactly into three bf16 parts and the
  * six part products above 2^-24 relative weight go through bf16 matrix
  * cores with FP32 accumulation (the three omitted are below 2^-23 |a d|);
- * the device holds a second copy of A, 6 dp^2 bytes.  AUTO = F32. */
+ * the device holds a second copy of A, 6 dp^2 bytes.  AUTO = BF16X3. */
 typedef enum { SSO_CONTRACT_AUTO = 0, SSO_CONTRACT_F32 = 1, SSO_CONTRACT_BF16X3 = 2 } sso_contraction;
 
 typedef struct {

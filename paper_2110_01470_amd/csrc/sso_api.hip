@@ -43,10 +43,11 @@ struct Layout {
     int engine, storage;
 };
 
-// The DENSE generation kernel takes the split bf16 contraction.
+// The DENSE generation kernel takes the split bf16 contraction unless the
+// FP32 one is asked for.
 bool split_contraction(const sso_config &c)
 {
-    return c.kind == SSO_OBJ_DENSE && c.contraction == SSO_CONTRACT_BF16X3;
+    return c.kind == SSO_OBJ_DENSE && c.contraction != SSO_CONTRACT_F32;
 }
 
 Layout make_layout(const sso_config &c)

@@ -41,8 +41,8 @@ def test_split_generations(n, d, order):
 
 def test_split_full_size():
     """The dense workload at full size (N=16384, D=256) with the split
-    contraction, as the benchmark launches it."""
-    pair = split_pair(16384, 256)
+    contraction, as the benchmark launches it (the default contraction)."""
+    pair = split_pair(16384, 256, contraction="auto")
     pair.compare()
     pair.step(2)
 

@@ -87,7 +87,10 @@ def test_device_words_grid_and_store_paths(n, d, offset):
     ("sphere", 1, 1, "stream"), ("ripple", 1, 3, "resident"),
 ])
 def test_initialisation_matches_oracle(kind, n, d, engine):
-    pair = Pair(kind, n, d, lo=-10.0, hi=10.0, s_range=(-5.0, 5.0), seed=11, engine=engine)
+    # Dense swarms here take the FP32 contraction (the split one, the
+    # default, has its own tests).
+    pair = Pair(kind, n, d, lo=-10.0, hi=10.0, s_range=(-5.0, 5.0), seed=11, engine=engine,
+                contraction="f32")
     pair.compare()
     # P^0 = X^0 and the trace of the initialisation counts every particle.
     fg, gi, im = pair.gpu.trace(0, 1)
@@ -191,7 +194,8 @@ def test_u24_storage_rejects_off_grid_state():
                                        (65, 255, oracle.ORDER_GPS), (17, 1, oracle.ORDER_GPS)])
 def test_dense_generations(n, d, order):
     cg, cp, cw = (0.4, 0.7, 0.9) if order == oracle.ORDER_GPS else (0.8, 0.6, 0.3)
-    pair = wl_pair("dense_n16384_d256", n=n, d=d, order=order, cg=cg, cp=cp, cw=cw)
+    pair = wl_pair("dense_n16384_d256", n=n, d=d, order=order, cg=cg, cp=cp, cw=cw,
+                   contraction="f32")
     pair.step(20)
 
 
@@ -212,8 +216,8 @@ def test_ripple_n65536_d1000_full_size(storage):
 
 
 def test_dense_n16384_d256_full_size():
-    """The dense workload at full size, as the benchmark launches it."""
-    pair = wl_pair("dense_n16384_d256")
+    """The dense workload at full size with the FP32 contraction."""
+    pair = wl_pair("dense_n16384_d256", contraction="f32")
     pair.compare()
     pair.step(2)
 
