@@ -299,11 +299,10 @@ double orc_fitness(int kind, uint32_t d, const float *x, const float *s, const f
 double orc_fitness_scale(int kind, uint32_t d, const float *x, const float *s, const float *w,
                          const float *a)
 {
-    if (kind < ORC_F1 || kind > ORC_F9) {
-        if (kind == ORC_SPHERE) return orc_fitness(kind, d, x, s, w, a);
-        /* RIPPLE and DENSE: sums of non-negative terms */
-        return orc_fitness(kind, d, x, s, w, a);
-    }
+    (void)s; (void)w; (void)a;
+    /* Defined for Table 3.2's functions only (their FP32 error bound); the
+     * shifted objectives have none here. */
+    if (kind < ORC_F1 || kind > ORC_F9) return NAN;
     double *t = (double *)malloc(sizeof(double) * (d ? d : 1));
     double *u = (double *)malloc(sizeof(double) * (d ? d : 1));
     const double f = paper_function(kind, d, x, t, u, 1);
@@ -514,6 +513,7 @@ void orc_set_state(orc_swarm *sw, const float *x, const float *p, const float *f
     memcpy(sw->x, x, sizeof(float) * nd);
     memcpy(sw->p, p, sizeof(float) * nd);
     memcpy(sw->fp, fp, sizeof(float) * sw->n);
+#pragma omp parallel for num_threads(g_threads) schedule(static)
     for (uint32_t i = 0; i < sw->n; ++i) {
         sw->fp64[i] = fitness_of(sw, sw->p + (size_t)i * sw->d);
         sw->fx64[i] = fitness_of(sw, sw->x + (size_t)i * sw->d);

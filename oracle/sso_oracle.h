@@ -88,10 +88,11 @@ float orc_fresh_value(const orc_rule *r, uint32_t word);
 double orc_fitness(int kind, uint32_t d, const float *x, const float *s, const float *w,
                    const float *a);
 
-/* Magnitude of the quantities the objective adds up at x (the same sums
- * with every term taken by absolute value and every difference as a sum of
- * magnitudes): the scale against which an FP32 evaluation's rounding error
- * is bounded.  Equals f for SPHERE, F1, F2 (all terms non-negative). */
+/* Magnitude of the quantities a Table 3.2 function adds up at x (the same
+ * sums with every term taken by absolute value and every difference as a sum
+ * of magnitudes): the scale against which an FP32 evaluation's rounding
+ * error is bounded.  Equals f for F1 and F2 (all terms non-negative).  NaN
+ * for every other kind (s, w and a are not used). */
 double orc_fitness_scale(int kind, uint32_t d, const float *x, const float *s, const float *w,
                          const float *a);
 

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "sso_oracle.c")
 PINS = ["tests/test_oracle_philox.py", "tests/test_oracle_rule.py",
         "tests/test_oracle_objectives.py", "tests/test_oracle_swarm.py",
-        "tests/test_oracle_gradient.py", "tests/test_oracle_paper.py"]
+        "tests/test_oracle_gradient.py", "tests/test_oracle_paper.py",
+        "tests/test_oracle_convergence.py"]
 
 MUTANTS = {
     "philox multipliers swapped": (
@@ -75,6 +76,7 @@ MUTANTS = {
         ("    /* Evaluate, then Algorithm 3: replace the pBest on a strict improvement. */",
          "    update_gbest(sw);\n    /* Evaluate, then Algorithm 3: replace the pBest on a strict improvement. */"),
         ("    /* Algorithm 4. */\n    update_gbest(sw);\n    sw->t += 1;", "    sw->t += 1;")],
+    "NaN pBest never replaced": ("    if (isnan(b)) return 1;", "    if (isnan(b)) return 0;"),
     "pBest kept forever": ("memcpy(sw->p + (size_t)i * d, xi, sizeof(float) * d);\n            sw->fp[i] = f32;",
                            "sw->fp[i] = f32;"),
 }

@@ -126,6 +126,16 @@ def test_scale_bounds_the_value(kind):
             assert sc == v
 
 
+def test_fitness_scale_is_only_defined_for_table_3_2():
+    """The shifted objectives have no scale: the call returns NaN for them,
+    so nothing can lean on an undefined bound."""
+    x = np.ones(8, np.float32)
+    s = np.zeros(8, np.float32)
+    for kind, w, a in ((oracle.SPHERE, None, None), (oracle.RIPPLE, np.ones(8, np.float32), None),
+                       (oracle.DENSE, None, np.eye(8, dtype=np.float32))):
+        assert np.isnan(oracle.fitness_scale(kind, x, s, w, a))
+
+
 @pytest.mark.parametrize("kind", range(oracle.F1, oracle.F9 + 1))
 def test_swarm_runs_on_each_function(kind):
     """A swarm on each function (no shift arrays): the pBest fitness never

@@ -1,5 +1,6 @@
 """Pins for the oracle's integer form of Eq. (2.1) and its draws on [varMin, varMax]."""
 import math
+import os
 from fractions import Fraction
 
 import numpy as np
@@ -77,8 +78,16 @@ def test_branch_frequencies_match_interval_widths():
     cg, cp, cw = 0.4, 0.7, 0.9
     r = oracle.Rule(cg, cp, cw, -100.0, 100.0)
     th = np.array(r.thresholds, dtype=np.uint64)
-    w = oracle.words(11, 0, 1, 2000, 1000).ravel().astype(np.uint64)
-    b = (w >= th[0]).astype(int) + (w >= th[1]) + (w >= th[2])
+    # 1.2e7 words (12000 particles x 1000 variables of one generation).
+    used = oracle.set_threads(min(8, os.cpu_count() or 1))
+    try:
+        w = oracle.words(11, 0, 1, 12000, 1000).ravel()
+    finally:
+        oracle.set_threads(1)
+    del used
+    b = (w >= np.uint32(th[0])).astype(np.int8)
+    b += w >= np.uint32(th[1])
+    b += w >= np.uint32(th[2])
     counts = np.bincount(b, minlength=4)
     probs = np.array([cg, cp - cg, cw - cp, 1.0 - cw])
     n = w.size

@@ -213,6 +213,37 @@ def test_lowest_index_wins_exact_ties():
     assert oracle.argmin(np.array([3, np.nan, 1, 1, np.inf], np.float32)) == 2
     assert oracle.argmin(np.array([np.nan, np.nan], np.float32)) == 0
     assert oracle.argmin(np.array([np.nan, np.inf], np.float32)) == 1
+    # -0 and +0 are the same fitness: the lower index wins either way round.
+    assert oracle.argmin(np.array([1, -0.0, 0.0], np.float32)) == 1
+    assert oracle.argmin(np.array([1, 0.0, -0.0], np.float32)) == 1
+
+
+def test_nan_orders_above_every_number_in_pbest_updates():
+    """Algorithm 3 with NaN ordered above every number (as in the argmin): a
+    pBest whose fitness is NaN is replaced by any number, and a NaN fitness
+    never replaces a pBest."""
+    n, d = 5, 4
+    s = np.zeros(d, np.float32)
+    sw = oracle.Swarm(n, d, oracle.SPHERE, -1.0, 1.0, 0.0, 0.0, 0.0, 7, s)
+    sw.init()
+    x, p, fp = sw.x.copy(), sw.p.copy(), sw.fp.copy()
+    fp[[1, 3]] = np.nan
+    fp[[0, 2, 4]] = 0.0  # nothing can improve on 0
+    sw.set_state(x, p, fp, 0)
+    assert sw.gidx == 0
+    sw.step()
+    assert list(sw.improved) == [0, 1, 0, 1, 0]
+    assert np.all(np.isfinite(sw.fp)) and np.all(sw.fp[[0, 2, 4]] == 0.0)
+    # A NaN objective (shift NaN in one coordinate): every fitness is NaN,
+    # so after initialisation nothing is ever replaced and gBest stays 0.
+    s_nan = s.copy()
+    s_nan[2] = np.nan
+    sw = oracle.Swarm(n, d, oracle.SPHERE, -1.0, 1.0, 0.4, 0.7, 0.9, 7, s_nan)
+    sw.init()
+    p0 = sw.p.copy()
+    sw.run(3)
+    assert np.all(np.isnan(sw.fp)) and sw.improved.sum() == 0
+    assert np.array_equal(sw.p, p0) and sw.gidx == 0
 
 
 @pytest.mark.parametrize("kind", ["ripple", "dense", "f3"])
