@@ -5,8 +5,12 @@ fitness, pBest update, gBest argmin) -- one launch of the fused generation
 kernel.  The default workload is the large ripple swarm (N=65536 particles,
 D=1000 FP32 variables, 1000 generations).  Timing: W warm-up generations on
 a throw-away swarm, then a fresh swarm is initialised (untimed, state already
-resident in HBM) and exactly K generations 1..K are timed with HIP events on
-the stream the kernels run on.
+resident in HBM).  When K is below the workload's T generations, that swarm
+first runs generations 1..T-K untimed, and the last K generations T-K+1..T of
+the run are timed, so the window is the run's steady state (in the first
+generations most particles improve, and an improved particle's position row
+is its pBest row, so it reads one row instead of two); otherwise generations
+1..K are timed.  Timing uses HIP events on the stream the kernels run on.
 
 Prints one JSON line:
   value    = N * D * K / seconds  (particle-variable updates per second,
@@ -60,18 +64,28 @@ def kernel_hash(kind):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(wl):
+def measured_traffic(wl, window=None, key=None):
     """HBM bytes per launch from the committed counter summary, or None if the
-    kernel changed since the counters were taken."""
+    kernel changed since the counters were taken or they cover another window
+    of generations than the line times."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            rec = json.load(fh).get(wl.name)
+            rec = json.load(fh).get(key or wl.name)
     except (OSError, ValueError):
         return None
     kind = "batch" if hasattr(wl, "count") else wl.kind
     if not rec or rec.get("kernel_hash") != kernel_hash(kind):
         return None
+    if window is not None and rec.get("timed_generations") != list(window):
+        return None
     return rec.get("bytes_per_launch")
+
+
+def timed_window(wl, steps):
+    """First and last generation of the timed window: the run's last `steps`
+    generations when they are fewer than its T, else 1..steps."""
+    first = wl.generations - steps + 1 if steps < wl.generations else 1
+    return first, first + steps - 1
 
 
 def time_gpu(wl, steps, warmup, engine, contraction="auto"):
@@ -89,6 +103,9 @@ def time_gpu(wl, steps, warmup, engine, contraction="auto"):
         warm.close()
         del warm
     sw = Swarm(*args, engine=engine, contraction=contraction, stream=stream)
+    first, _ = timed_window(wl, steps)
+    if first > 1:
+        sw.run(first - 1)  # untimed: generations 1..first-1 of the same run
     stream.synchronize()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -285,6 +302,41 @@ def copy_calibration(nbytes, reps=5):
                       "GBps_read_plus_write": 2 * nbytes / sec / 1e9}), flush=True)
 
 
+def profile_window(path, kernel_regex, last):
+    """Summary of the last `last` dispatches of the kernels whose name matches
+    `kernel_regex` in a rocprofv3 CSV: a kernel trace (durations, ns) or a
+    counter collection (each counter's per-dispatch value).  This is how the
+    committed profile summaries relate a whole profiled bench run to the
+    generations its line times (the run's last K)."""
+    import csv
+    import re
+
+    pat = re.compile(kernel_regex)
+    with open(path, newline="") as fh:
+        rows = [r for r in csv.DictReader(fh) if pat.search(r.get("Kernel_Name", ""))]
+    out = {"file": os.path.basename(path), "kernel_regex": kernel_regex, "last": last}
+    if rows and "Counter_Name" in rows[0]:
+        by = {}
+        for r in rows:
+            by.setdefault(r["Counter_Name"], []).append(
+                (int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0), float(r["Counter_Value"])))
+        for name, vals in sorted(by.items()):
+            vals.sort()
+            v = np.array([x for _, x in vals[-last:]])
+            out[name] = {"dispatches": len(vals), "window_mean": float(v.mean()),
+                         "window_min": float(v.min()), "window_max": float(v.max()),
+                         "all_mean": float(np.mean([x for _, x in vals]))}
+    else:
+        ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+                    for r in rows)
+        dur = np.array([d for _, d in ev], dtype=np.float64)
+        w = dur[-last:]
+        out.update({"dispatches": int(dur.size), "window_mean_ns": float(w.mean()),
+                    "window_min_ns": float(w.min()), "window_max_ns": float(w.max()),
+                    "all_mean_ns": float(dur.mean())})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     from paper_2110_01470_amd.inputs import BATCH_WORKLOADS, PAPER_WORKLOADS, WORKLOADS
 
@@ -313,8 +365,16 @@ def main():
                     help="only measure the copy-bandwidth and Philox-rate ceilings")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--profile-window", metavar="CSV",
+                    help="only summarise the last --window dispatches of --kernel-regex in a "
+                         "rocprofv3 kernel-trace or counter CSV (no GPU)")
+    ap.add_argument("--kernel-regex", default=r"sso::k_")
+    ap.add_argument("--window", type=int, default=20)
     args = ap.parse_args()
 
+    if args.profile_window:
+        profile_window(args.profile_window, args.kernel_regex, args.window)
+        return
     if args.copy_bytes:
         copy_calibration(args.copy_bytes)
         return
@@ -343,7 +403,9 @@ def main():
         bench_polish(wl, args)
         return
     steps = args.steps if args.steps is not None else wl.generations
-    log(f"workload {wl.name}: N={wl.n} D={wl.d} steps={steps} warmup={args.warmup}")
+    window = timed_window(wl, steps)
+    log(f"workload {wl.name}: N={wl.n} D={wl.d} steps={steps} warmup={args.warmup}, "
+        f"timed generations {window[0]}..{window[1]}")
     ms, fg, gen = time_gpu(wl, steps, args.warmup, args.engine, args.contraction)
     sec = ms / 1e3
     updates = wl.n * wl.d * steps
@@ -360,19 +422,20 @@ def main():
         achieved = flop / (ms_per_step / 1e3) / 1e12
         fp32_eq = achieved / 6 / FP32_MATRIX_PEAK_TFLOPS
         roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_MATRIX_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / BF16_MATRIX_PEAK_TFLOPS, "traffic": None,
+                    "unit": "TFLOP/s", "frac": achieved / BF16_MATRIX_PEAK_TFLOPS,
+                    "traffic": measured_traffic(wl, window, wl.name + "/bf16x3"),
                     "fp32_equivalent_frac": fp32_eq}
     elif wl.kind == "dense":
         flop = 2.0 * wl.n * wl.d * wl.d
         achieved = flop / (ms_per_step / 1e3) / 1e12
         roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MATRIX_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": achieved / FP32_MATRIX_PEAK_TFLOPS,
-                    "traffic": measured_traffic(wl)}
+                    "traffic": measured_traffic(wl, window, wl.name + "/f32")}
     else:
         byt = BYTES_PER_UPDATE * wl.n * wl.d
         achieved = byt / (ms_per_step / 1e3) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl)}
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl, window)}
 
     cpu_gens = args.cpu_gens
     if cpu_gens is None:
@@ -410,7 +473,8 @@ def main():
         "dtype": "bf16x3" if split else "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "objective": wl.kind, "n": wl.n, "d": wl.d,
-                   "generations": steps, "engine": args.engine,
+                   "generations": max(steps, wl.generations),
+                   "timed_generations": list(window), "engine": args.engine,
                    **({"contraction": "f32" if args.contraction == "f32" else "bf16x3"}
                       if wl.kind == "dense" else {})},
         "roofline": roofline,
@@ -712,7 +776,7 @@ def bench_batch(bw, args):
     byt = BYTES_PER_UPDATE * total
     achieved = byt / (ms_per_step / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(bw)}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(bw, (1, steps))}
     cpu = None
     if args.cpu_gens is None or args.cpu_gens > 0:
         gens = args.cpu_gens or 1

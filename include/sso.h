@@ -137,21 +137,30 @@ typedef struct sso_ctx sso_ctx;
 /* Bytes of device workspace the configuration needs; 0 if it is invalid. */
 size_t sso_workspace_bytes(const sso_config *cfg);
 
-/* Validates cfg, lays the state out in the workspace, uploads s, w, a
+/* Kernel function (I) of Sec. 2.3.1 and the initialisation that opens
+ * Algorithm 2 (Sec. 3.3), its transfer of the problem to the device included.
+ * Validates cfg, lays the state out in the workspace, uploads s, w, a
  * (synchronously), and enqueues the initialisation on `hip_stream`
- * (a hipStream_t; NULL = the null stream): X^0 uniform on [lo, hi] from the
- * Philox words of generation 0, P^0 = X^0, fP^0 = f(X^0), gBest^0 = the
- * lowest-index argmin.  *out receives the context; on error *out is NULL. */
+ * (a hipStream_t; NULL = the null stream): X^0 uniform on [lo, hi] (Table
+ * 3.1's range) from the Philox words of generation 0, P^0 = X^0,
+ * fP^0 = f(X^0), gBest^0 = the lowest-index argmin (Algorithm 4).  *out
+ * receives the context; on error *out is NULL. */
 int sso_init(const sso_config *cfg, void *dev_workspace, size_t workspace_bytes,
              void *hip_stream, sso_ctx **out);
 
-/* Enqueue one generation t -> t + 1 (Algorithm 2's loop body). */
+/* Enqueue one generation t -> t + 1: one pass of the loop body of
+ * Algorithm 2 (Sec. 3.3), i.e. the search of kernel function (C) (Eq. 2.1
+ * for every variable of every particle), the evaluation of kernel function
+ * (E), and the update (U) of the pBests (Algorithm 3) and of gBest
+ * (Algorithm 4), all reading only generation t's state. */
 int sso_step(sso_ctx *ctx);
 
-/* Enqueue `generations` generations. */
+/* Enqueue `generations` generations: Algorithm 2's loop over iterations
+ * (Sec. 3.3), with no host transfer between them. */
 int sso_run(sso_ctx *ctx, uint32_t generations);
 
-/* Synchronise, then copy gBest out: g_out host [d] (may be NULL), its FP32
+/* Algorithm 2's final step (Sec. 3.3), sending the result back to the host.
+ * Synchronise, then copy gBest out: g_out host [d] (may be NULL), its FP32
  * fitness, its particle index, and the number of generations done. */
 int sso_get_best(sso_ctx *ctx, float *g_out, float *f_out, uint32_t *idx_out,
                  uint64_t *gen_out);

@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
     f += __shfl_xor(f, 32, 64);
 
     const bool owner = half == 0 && valid;
-    const bool improved = owner && (INIT || f < fpi);
+    const bool improved = owner && (INIT || improves(f, fpi));
     uint32_t row = prow;
     float fnew = fpi;
     if (improved) {
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(256) void k_dense3(SwarmDev S, uint32_t t)
     f += __shfl_xor(f, 16, 64);
     f += __shfl_xor(f, 32, 64);
 
-    const bool improved = valid && (INIT || f < fpi);
+    const bool improved = valid && (INIT || improves(f, fpi));
     uint32_t row = prow;
     float fnew = fpi;
     if (improved) {

@@ -258,8 +258,8 @@ __global__ __launch_bounds__(kGradBlock) void k_dense_grad(SwarmDev S, GradArgs 
             }
         }
         const float f = fitness();
-        // Algorithm 3's rule: a strict improvement replaces the pBest (NaN never).
-        const bool improved = valid && f < fpi;
+        // Algorithm 3's rule: a strict improvement replaces the pBest (NaN ordered last).
+        const bool improved = valid && improves(f, fpi);
         const uint32_t nrow = alias ? 1u - prow : prow;
         if (improved) {
             // An aliased pBest is also the position: the polished point goes

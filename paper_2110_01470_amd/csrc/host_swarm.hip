@@ -104,6 +104,14 @@ void resolve(const sso_config &c, int *engine, int *storage)
 
 int validate(const sso_config *c, std::string *why)
 {
+    const char *msg = "";
+    const int rc = validate_msg(c, &msg);
+    if (rc != SSO_OK) *why = msg;
+    return rc;
+}
+
+int validate_msg(const sso_config *c, const char **why)
+{
     auto bad = [&](int code, const char *msg) {
         *why = msg;
         return code;

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, ui
         }
 #pragma unroll
         for (int m = L / 2; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-        const bool improved = valid && acc < fp;
+        const bool improved = valid && improves(acc, fp);
         if (improved) {
             pv = xv;
             fp = acc;

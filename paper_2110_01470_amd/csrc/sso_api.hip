@@ -35,7 +35,19 @@ namespace {
 
 using namespace sso::host;
 
-thread_local std::string g_err;
+// Detail of the calling thread's last failed context-less call, kept in a
+// fixed buffer so that setting it allocates nothing.
+struct ErrText {
+    char buf[512];
+    ErrText &operator=(const char *m)
+    {
+        std::snprintf(buf, sizeof buf, "%s", m);
+        return *this;
+    }
+    ErrText &operator=(const std::string &m) { return *this = m.c_str(); }
+    const char *c_str() const { return buf; }
+};
+thread_local ErrText g_err;
 
 struct Layout {
     size_t rows, fp, st, s, w, a, at, a3, keys, cnt, sub, total;
@@ -130,12 +142,63 @@ float polish_step_size(sso_ctx *ctx, float lr)
     return s > 0.0 ? (float)(0.05 / (s * s)) : 0.0f;
 }
 
+// Lanes per particle of a STREAM swarm: the configured count, else the
+// default rule.
+uint32_t swarm_lanes(const sso_config &c, const Layout &L)
+{
+    return (L.engine == SSO_ENGINE_STREAM && c.lanes) ? c.lanes : stream_lanes(c.d, L.storage);
+}
+
+// Points the swarm's device arrays at their regions of the workspace `base`
+// and fills in the sizes and the method's parameters.
+void bind_layout(const sso_config &c, const Layout &L, char *base, uint32_t lanes, SwarmDev &S)
+{
+    S.rows = (float *)(base + L.rows);
+    S.fp = (float *)(base + L.fp);
+    S.st = (uint32_t *)(base + L.st);
+    S.s = (const float *)(base + L.s);
+    S.w = c.kind == SSO_OBJ_RIPPLE ? (const float *)(base + L.w) : nullptr;
+    S.a = c.kind == SSO_OBJ_DENSE ? (const float *)(base + L.a) : nullptr;
+    S.at = c.kind == SSO_OBJ_DENSE ? (const float *)(base + L.at) : nullptr;
+    S.a3 = split_contraction(c) ? (const uint16_t *)(base + L.a3) : nullptr;
+    S.keys = (unsigned long long *)(base + L.keys);
+    S.cnt = (uint32_t *)(base + L.cnt);
+    S.sub = (unsigned long long *)(base + L.sub);
+    S.buf = (uint64_t)c.n * L.stride;
+    S.n = c.n;
+    S.d = c.d;
+    S.dp = L.dp;
+    S.stride = L.stride;
+    S.storage = L.storage;
+    S.chunks = (c.d + 3) / 4;
+    S.trace_cap = L.trace_cap;
+    set_params(c, S);
+    S.nsub = kSubSlots;
+    S.lanes = lanes;
+}
+
+// Enqueues generations t_first .. t_first + count - 1 of a swarm with no
+// polish schedule (one launch per generation, or one RESIDENT launch for all).
+hipError_t enqueue_generations(const SwarmDev &S, int engine, uint32_t lanes, uint64_t t_first,
+                               uint32_t count, hipStream_t stream)
+{
+    if (count == 0) return hipSuccess;
+    if (engine == SSO_ENGINE_RESIDENT) return (hipError_t)launch_resident(S, (uint32_t)t_first, count, stream);
+    for (uint32_t k = 0; k < count; ++k) {
+        const uint32_t t = (uint32_t)(t_first + k);
+        const int e = S.kind == SSO_OBJ_DENSE ? launch_dense_generation(S, t, stream)
+                                              : launch_stream_generation(S, t, lanes, stream);
+        if (e) return (hipError_t)e;
+    }
+    return hipSuccess;
+}
+
 int launch_generations(sso_ctx *ctx, uint64_t t_first, uint32_t count)
 {
     const SwarmDev &S = ctx->S;
-    if (ctx->engine == SSO_ENGINE_RESIDENT) {
-        const int e = launch_resident(S, (uint32_t)t_first, count, ctx->stream);
-        if (e) return hip_fail(&ctx->err, (hipError_t)e, "resident kernel launch");
+    if (!ctx->polish_every) {
+        const hipError_t e = enqueue_generations(S, ctx->engine, ctx->lanes, t_first, count, ctx->stream);
+        if (e != hipSuccess) return hip_fail(&ctx->err, e, "generation kernel launch");
         return SSO_OK;
     }
     const float lr = ctx->polish_every ? polish_step_size(ctx, ctx->polish_lr) : 0.0f;
@@ -217,35 +280,15 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
     const int engine = L.engine;
     ctx->engine = engine;
     ctx->storage = L.storage;
-    ctx->lanes = (engine == SSO_ENGINE_STREAM && cfg->lanes) ? cfg->lanes : stream_lanes(cfg->d, L.storage);
+    ctx->lanes = swarm_lanes(*cfg, L);
 
-    char *base = (char *)ws;
     SwarmDev &S = ctx->S;
-    S.rows = (float *)(base + L.rows);
-    S.fp = (float *)(base + L.fp);
-    S.st = (uint32_t *)(base + L.st);
-    S.s = (const float *)(base + L.s);
-    S.w = cfg->kind == SSO_OBJ_RIPPLE ? (const float *)(base + L.w) : nullptr;
-    S.a = cfg->kind == SSO_OBJ_DENSE ? (const float *)(base + L.a) : nullptr;
-    S.at = cfg->kind == SSO_OBJ_DENSE ? (const float *)(base + L.at) : nullptr;
-    S.a3 = split_contraction(*cfg) ? (const uint16_t *)(base + L.a3) : nullptr;
-    S.keys = (unsigned long long *)(base + L.keys);
-    S.cnt = (uint32_t *)(base + L.cnt);
-    S.sub = (unsigned long long *)(base + L.sub);
-    S.buf = (uint64_t)cfg->n * L.stride;
-    S.n = cfg->n;
-    S.d = cfg->d;
-    S.dp = L.dp;
-    S.stride = L.stride;
-    S.storage = L.storage;
-    S.chunks = (cfg->d + 3) / 4;
-    S.trace_cap = L.trace_cap;
-    set_params(*cfg, S);
-    S.nsub = kSubSlots;
-    S.lanes = ctx->lanes;
+    bind_layout(*cfg, L, (char *)ws, ctx->lanes, S);
 
-    std::string *err = &g_err;
+    std::string err_text;
+    std::string *err = &err_text;
     auto fail = [&](int code) {
+        g_err = err_text;
         delete ctx;
         return code;
     };
@@ -283,7 +326,7 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
     if (e != hipSuccess) return fail(hip_fail(err, e, "synchronise uploads"));
     rc = launch_init(ctx);
     if (rc != SSO_OK) {
-        g_err = ctx->err;
+        err_text = ctx->err;
         return fail(rc);
     }
     *out = ctx;

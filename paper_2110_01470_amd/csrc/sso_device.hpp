@@ -380,6 +380,14 @@ __device__ __forceinline__ uint32_t orderable(float f)
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
+// Algorithm 3's strict improvement in the same order as the gBest key: NaN
+// sorts above every number, so a NaN pBest fitness is replaced by any number
+// and a NaN fitness never replaces a pBest; -0 and +0 are equal.
+__device__ __forceinline__ bool improves(float f, float fp)
+{
+    return f < fp || (fp != fp && f == f);
+}
+
 __device__ __forceinline__ unsigned long long gbest_key(float f, uint32_t i, uint32_t row)
 {
     return ((unsigned long long)orderable(f) << 32) | ((unsigned long long)i << 1) | row;

@@ -22,6 +22,8 @@ uint32_t round_up(uint32_t x, uint32_t m);
 uint64_t threshold(double c);
 // SSO_OK or an error code with the reason in *why.
 int validate(const sso_config *c, std::string *why);
+// The same checks with the reason as a static string (no allocation).
+int validate_msg(const sso_config *c, const char **why);
 // Engine and row storage a valid configuration resolves to.
 void resolve(const sso_config &c, int *engine, int *storage);
 int hip_fail(std::string *err, hipError_t e, const char *what);

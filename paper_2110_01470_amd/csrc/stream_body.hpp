@@ -190,8 +190,8 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
             if ((uint32_t)m < L) acc += __shfl_xor(acc, m, 64);
     }
 
-    // Algorithm 3: replace the pBest on a strict improvement (NaN never does).
-    const bool improved = valid && (INIT || acc < fpi);
+    // Algorithm 3: replace the pBest on a strict improvement (NaN ordered last).
+    const bool improved = valid && (INIT || improves(acc, fpi));
     uint32_t row = prow;
     float fnew = fpi;
     if (improved) {
