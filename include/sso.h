@@ -217,6 +217,33 @@ int sso_polish(sso_ctx *ctx, uint32_t steps, float lr, float *lr_used);
 /* Free the context (not the workspace).  NULL is allowed. */
 void sso_destroy(sso_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Allocation-free run, for callers that cannot allocate: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * The same initialisation and generations as sso_init followed by
+ * sso_run(generations) (same kernels, same results bit for bit), with the
+ * swarm's state held in a device array the library owns instead of a caller
+ * workspace and no context; then gBest after the last generation goes to
+ * device memory: dev_g [d] FP32 position, *dev_f its FP32 fitness, *dev_idx
+ * its particle index (each may be NULL).  Enqueued on `hip_stream` (NULL =
+ * the null stream); returns without synchronising; the host arrays s and w
+ * are read during the call.
+ *
+ * Limits: objectives SPHERE, RIPPLE and F1..F9 (DENSE returns
+ * SSO_E_UNSUPPORTED); the state sso_workspace_bytes(cfg) reports must fit the
+ * array, SSO_STATIC_SCRATCH_BYTES (64 MiB), else SSO_E_NOMEM and nothing is
+ * enqueued.  Each GPU the library runs on holds its own array until the
+ * process ends.  Every call on one GPU uses that GPU's array and leaves its
+ * state there until the next call: calls that overlap on one GPU (from
+ * other streams or host threads) race and give undefined results.  On its
+ * success path the call allocates nothing, host or device; the error detail
+ * is in sso_last_error(NULL).
+ * ------------------------------------------------------------------------ */
+#define SSO_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int sso_run_static(const sso_config *cfg, uint32_t generations, void *hip_stream,
+                   float *dev_g, float *dev_f, uint32_t *dev_idx);
+
 /* Static text for an SSO_* code. */
 const char *sso_strerror(int code);
 

@@ -83,6 +83,7 @@ def load():
         "sso_eval": (ctypes.c_int, [P, P, u32, P, P, P]),
         "sso_polish": (ctypes.c_int, [P, u32, ctypes.c_float, P]),
         "sso_destroy": (None, [P]),
+        "sso_run_static": (ctypes.c_int, [cfgp, u32, P, P, P, P]),
         "sso_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sso_last_error": (ctypes.c_char_p, [P]),
         "sso_batch_workspace_bytes": (ctypes.c_size_t, [cfgp, u32]),
@@ -137,6 +138,35 @@ def workspace_bytes(cfg):
     if nbytes == 0:
         raise SSOError(E_INVAL, lib.sso_last_error(None).decode())
     return nbytes
+
+
+STATIC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def run_static(n, d, kind, lo, hi, cg, cp, cw, seed, s, w=None, generations=0, device="cuda",
+               stream=None, **cfg_kw):
+    """sso_run_static: initialise and run `generations` generations in the
+    library's static device array (no workspace, no context), gBest written to
+    device tensors.  Returns (g [d], fG, gidx) after synchronising the stream.
+    Raises SSOError with the library's code (SSO_E_NOMEM when the swarm's state
+    exceeds STATIC_SCRATCH_BYTES)."""
+    import torch
+
+    lib = load()
+    cfg, keep = make_config(n, d, kind, lo, hi, cg, cp, cw, seed, s, w, **cfg_kw)
+    dev = torch.device(device)
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    g = torch.empty(d, dtype=torch.float32, device=dev)
+    f = torch.empty(1, dtype=torch.float32, device=dev)
+    idx = torch.empty(1, dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        rc = lib.sso_run_static(ctypes.byref(cfg), generations, ctypes.c_void_p(stream.cuda_stream),
+                                g.data_ptr(), f.data_ptr(), idx.data_ptr())
+    if rc != OK:
+        raise SSOError(rc, lib.sso_last_error(None).decode())
+    stream.synchronize()
+    del keep
+    return (g.cpu().numpy(), float(f.cpu()[0]), int(idx.cpu().numpy().view(np.uint32)[0]))
 
 
 class Swarm:

@@ -6,10 +6,12 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "sso.h"
+#include "sso_device.hpp"
 #include "sso_host.hpp"
 #include "sso_layout.hpp"
 
@@ -226,9 +228,157 @@ int launch_init(sso_ctx *ctx)
     return SSO_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free run (sso_run_static).  The swarm's state lives in one
+// library-owned device array per GPU instead of a caller workspace.  In host
+// code `scratch` names a host-side stand-in, not the device memory: host code
+// uses only the address hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticBytes = (size_t)SSO_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices];  // device address of `scratch` per device, once set up
+
+// The array's address on device `dev` (current), looked up on the first call
+// for that device; *why is set on failure.
+void *static_scratch(int dev, const char **why)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        *why = "device ordinal beyond the allocation-free run's device table (64)";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr || ((uintptr_t)ptr & 255u)) {
+            *why = "hipGetSymbolAddress of the static state array failed";
+            return nullptr;
+        }
+        g_static_ptr[dev] = ptr;
+    }
+    return g_static_ptr[dev];
+}
+
+// Zero padding of s and w beyond d (the whole of s when there is no shift):
+// the kernels read whole chunks of the staged arrays.  A kernel rather than a
+// memset, like the trace fill.
+__global__ void k_static_pad(float *s, float *w, uint32_t from_s, uint32_t d, uint32_t dp)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < dp && j >= from_s) s[j] = 0.0f;
+    if (w && j < dp && j >= d) w[j] = 0.0f;
+}
+
+// gBest of generation t into device memory: the lowest key over the 64
+// sub-slots of generation t's group (Algorithm 4's argmin, as the next
+// generation would take it), its FP32 fitness, particle index and position.
+__global__ __launch_bounds__(256) void k_best_out(SwarmDev S, uint32_t t, float *g, float *f,
+                                                  uint32_t *idx)
+{
+    __shared__ unsigned long long best;
+    if (threadIdx.x < 64u) {
+        const unsigned long long k = wave_min_u64(*sub_key(S, t % kGroups, threadIdx.x));
+        if (threadIdx.x == 0) best = k;
+    }
+    __syncthreads();
+    const unsigned long long key = best;
+    const uint32_t i = (uint32_t)key >> 1, row = (uint32_t)key & 1u;
+    const bool found = i < S.n;
+    if (threadIdx.x == 0) {
+        const uint32_t o = (uint32_t)(key >> 32);
+        const uint32_t b = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+        if (f) *f = found ? __uint_as_float(b) : __uint_as_float(0x7FC00000u);
+        if (idx) *idx = found ? i : 0xFFFFFFFFu;
+    }
+    if (!g || !found) return;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(S.rows) + row * S.buf + (size_t)i * S.stride;
+    for (uint32_t j = threadIdx.x; j < S.d; j += blockDim.x) {
+        float v;
+        if (S.storage == STORE_U24) {
+            const f4 q = StoreU24::value(S, StoreU24::load(src, j >> 2));
+            v = q[j & 3u];
+        } else {
+            v = __uint_as_float(src[j]);
+        }
+        g[j] = v;
+    }
+}
+
 }  // namespace
 
 extern "C" {
+
+int sso_run_static(const sso_config *cfg, uint32_t generations, void *stream, float *dev_g,
+                   float *dev_f, uint32_t *dev_idx)
+{
+    const char *why = "";
+    const int rc = validate_msg(cfg, &why);
+    if (rc != SSO_OK) {
+        g_err = why;
+        return rc;
+    }
+    if (cfg->kind == SSO_OBJ_DENSE) {
+        g_err = "the allocation-free run takes SPHERE, RIPPLE and F1..F9, not DENSE";
+        return SSO_E_UNSUPPORTED;
+    }
+    if (generations >= 0xFFFFFFFFu) {
+        g_err = "generations must be below 2^32 - 1";
+        return SSO_E_UNSUPPORTED;
+    }
+    const Layout L = make_layout(*cfg);
+    if (L.total > kStaticBytes) {
+        std::snprintf(g_err.buf, sizeof g_err.buf,
+                      "the swarm needs %zu bytes of device state; the allocation-free run's static "
+                      "array holds %zu (SSO_STATIC_SCRATCH_BYTES)",
+                      L.total, kStaticBytes);
+        return SSO_E_NOMEM;
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        g_err = "no HIP device";
+        return SSO_E_HIP;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_err = "library is built for gfx950";
+        return SSO_E_UNSUPPORTED;
+    }
+    char *base = (char *)static_scratch(dev, &why);
+    if (!base) {
+        g_err = why;
+        return SSO_E_HIP;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    SwarmDev S{};
+    const uint32_t lanes = swarm_lanes(*cfg, L);
+    bind_layout(*cfg, L, base, lanes, S);
+    auto hip_err = [&](hipError_t e, const char *what) {
+        std::snprintf(g_err.buf, sizeof g_err.buf, "%s: %s", what, hipGetErrorString(e));
+        return SSO_E_HIP;
+    };
+    hipError_t e = hipSuccess;
+    if (cfg->s)
+        e = hipMemcpyAsync((void *)S.s, cfg->s, sizeof(float) * cfg->d, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && cfg->kind == SSO_OBJ_RIPPLE)
+        e = hipMemcpyAsync((void *)S.w, cfg->w, sizeof(float) * cfg->d, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_err(e, "upload s, w");
+    hipLaunchKernelGGL(k_static_pad, dim3((L.dp + 255u) / 256u), dim3(256), 0, st, (float *)S.s,
+                       (float *)S.w, cfg->s ? cfg->d : 0u, cfg->d, L.dp);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_err(e, "padding kernel launch");
+    int k = launch_fill_trace(S, st);
+    if (!k) k = launch_stream_generation(S, 0, lanes, st);
+    if (k) return hip_err((hipError_t)k, "initialisation launch");
+    e = enqueue_generations(S, L.engine, lanes, 1, generations, st);
+    if (e != hipSuccess) return hip_err(e, "generation kernel launch");
+    hipLaunchKernelGGL(k_best_out, dim3(1), dim3(256), 0, st, S, generations, dev_g, dev_f, dev_idx);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_err(e, "gBest copy launch");
+    return SSO_OK;
+}
 
 size_t sso_workspace_bytes(const sso_config *cfg)
 {

@@ -25,7 +25,7 @@ def test_header_declares_the_boundary():
                      "sso_batch_run", "sso_batch_tune", "sso_batch_get_results", "sso_eval",
                      "sso_polish"):
         assert required in names
-    assert len(names) == 26
+    assert len(names) == 27
 
 
 def test_library_exports_every_declared_symbol():
@@ -118,6 +118,25 @@ def test_init_rejects_bad_workspace_before_touching_a_device():
     assert lib.sso_init(ctypes.byref(c), ctypes.c_void_p(4096), nbytes - 1, None,
                         ctypes.byref(ctx)) == binding.E_NOMEM
     assert ctx.value is None
+
+
+def test_static_run_rejects_before_touching_a_device():
+    """sso_run_static refuses invalid configurations, the dense objective and
+    swarms whose state exceeds its static array before any HIP call."""
+    lib = binding.load()
+    P = ctypes.c_void_p
+    assert lib.sso_run_static(None, 1, None, None, None, None) == binding.E_INVAL
+    c, keep = cfg(n=0)
+    assert lib.sso_run_static(ctypes.byref(c), 1, None, None, None, None) == binding.E_INVAL
+    c, keep = cfg(n=64, d=16, kind="dense", a=np.eye(16, dtype=np.float32))
+    assert lib.sso_run_static(ctypes.byref(c), 1, None, None, None, None) == binding.E_UNSUPPORTED
+    assert b"DENSE" in lib.sso_last_error(None)
+    # The ripple workload's state (about 400 MB) exceeds the 64 MiB array.
+    c, keep = cfg(n=65536, d=1000, kind="ripple", w=np.ones(1000, np.float32))
+    assert binding.workspace_bytes(c) > binding.STATIC_SCRATCH_BYTES
+    assert lib.sso_run_static(ctypes.byref(c), 5, None, P(4096), P(4096), P(4096)) == binding.E_NOMEM
+    msg = lib.sso_last_error(None).decode()
+    assert str(binding.STATIC_SCRATCH_BYTES) in msg and str(binding.workspace_bytes(c)) in msg
 
 
 def batch_cfgs(*changes):
