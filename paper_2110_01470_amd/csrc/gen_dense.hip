@@ -632,11 +632,313 @@ __global__ __launch_bounds__(256) void k_dense3(SwarmDev S, uint32_t t)
     wave_commit(S, t, blockIdx.x * 4u + wave, key, (improved && lg == 0) ? 1u : 0u);
 }
 
+// ---------------------------------------------------------------------------
+// Split contraction, eight waves (the default form of the split kernel).
+//
+// Same arithmetic as k_dense3 (three exact bf16 parts per FP32 operand, the
+// six part products above 2^-24 relative weight, FP32 accumulation), with
+// the 64 particles of a workgroup spread over eight waves, two per SIMD, so
+// that one wave's matrix-core work runs while the other selects or waits.
+//   Select: thread (particle pl = tid / 8, q = tid % 8) selects chunk
+//   8 m + q of its particle in step m (Eq. 2.1), writes it, and writes the
+//   three bf16 parts of d = x' - s into LDS in the B-operand layout of the MFMA: tile pl / 16,
+//   lane (pl % 16) + 16 (q / 2), elements 4 (q % 2) .. 4 (q % 2) + 3.
+//   Contract: wave w owns row blocks 2 w and 2 w + 1 of A for all four tiles
+//   of 16 particles: per step it reads 6 A operands (its row blocks, three
+//   parts) and 12 B operands (four tiles, three parts) from LDS for 48
+//   MFMAs, against 48 A and no B reads for 96 MFMAs per wave in k_dense3.
+//   Fitness: each wave's partial sum of y_k^2 over its 32 rows per particle
+//   meets the others' in LDS, added in wave order.
+// One barrier per step: step m + 1's A block and d parts are written during
+// step m into the buffers not read in step m.  A reaches LDS through
+// registers (plain loads, then LDS stores): with a global-to-LDS copy in
+// flight the compiler waits for every outstanding load before it uses any
+// loaded register, which would drain the prefetch of later steps each step.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// The three bf16 parts of four FP32 values.
+__device__ __forceinline__ void split3x4(f4 d, bf16x4 &h, bf16x4 &m, bf16x4 &l)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float v = d[j];
+        const __bf16 v1 = (__bf16)v;
+        const float r1 = v - (float)v1;
+        const __bf16 v2 = (__bf16)r1;
+        h[j] = v1;
+        m[j] = v2;
+        l[j] = (__bf16)(r1 - (float)v2);
+    }
+}
+
+template <int NB, bool EQ21, bool INIT, bool FULL_D>
+__global__ __launch_bounds__(512) void k_dense3w(SwarmDev S, uint32_t t)
+{
+    constexpr uint32_t STEPS = NB / 2;              // 32 variables per step
+    constexpr uint32_t STEP_U = NB * 3u * 64u;      // 16-byte units of A per step
+    constexpr uint32_t PER = (STEP_U + 511u) / 512u;
+    constexpr bool FULL = STEP_U % 512u == 0;
+    constexpr uint32_t B_U = 4u * 3u * 64u;         // 16-byte units of d parts per step
+    __shared__ f4 lda0[STEP_U];
+    __shared__ f4 lda1[STEP_U];
+    __shared__ f4 ldb0[B_U];
+    __shared__ f4 ldb1[B_U];
+    __shared__ float fpart[8][64];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const uint32_t pl = tid >> 3, q = tid & 7u;
+    const uint32_t ip = blockIdx.x * 64u + pl;
+    // A thread of a particle past the last one works as a copy of particle
+    // n - 1 (same rows and words, the same values to the same addresses) and
+    // its fitness is not used: the select has no branch.
+    const uint32_t ie = ip < S.n ? ip : S.n - 1u;
+    const uint32_t bsl = ((pl >> 4) * 3u * 64u + (pl & 15u) + 16u * (q >> 1)) * 2u + (q & 1u);
+    const f4 *a_pack = reinterpret_cast<const f4 *>(S.a3);
+
+    unsigned long long gkey = ~0ull;
+    if constexpr (!INIT) gkey = generation_key_load(S, t);
+    // The particle this thread decides for (wave 0): pBest fitness and state.
+    const uint32_t idec = blockIdx.x * 64u + tid;
+    const bool dvalid = tid < 64u && idec < S.n;
+    uint32_t st = ST_ALIAS, std_ = ST_ALIAS;
+    float fpi = 0.0f;
+    if (!INIT) {
+        st = S.st[ie];
+        if (dvalid) {
+            std_ = S.st[idec];
+            fpi = S.fp[idec];
+        }
+    }
+    const size_t ioff = (size_t)ie * S.stride;
+    const f4 *s4 = reinterpret_cast<const f4 *>(S.s);
+
+    // Step m's block of A parts: loaded into registers, written to LDS
+    // buffer b later.
+    f4 ra[PER];
+    auto load_a = [&](uint32_t m) {
+#pragma unroll
+        for (uint32_t r = 0; r < PER; ++r) {
+            const uint32_t u = tid + r * 512u;
+            if (FULL || u < STEP_U) ra[r] = a_pack[(size_t)m * STEP_U + u];
+        }
+    };
+    auto store_a = [&](uint32_t b) {
+        f4 *dst = b ? lda1 : lda0;
+#pragma unroll
+        for (uint32_t r = 0; r < PER; ++r) {
+            const uint32_t u = tid + r * 512u;
+            if (FULL || u < STEP_U) dst[u] = ra[r];
+        }
+    };
+    // A block 0 does not depend on gBest: requested before the key arrives.
+    load_a(0);
+    const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
+    // Operands of the select, two steps' worth: set m & 1 holds step m's
+    // pBest, position, gBest and shift chunks.
+    f4 pv[2], xv[2], gv[2], sv[2], row0 = zero4, row1 = zero4;
+    pv[0] = pv[1] = xv[0] = xv[1] = gv[0] = gv[1] = sv[0] = sv[1] = zero4;
+    if (FULL_D || q < S.chunks) {
+        sv[0] = s4[q];
+        if constexpr (!INIT) {
+            row0 = reinterpret_cast<const f4 *>(S.rows + ioff)[q];
+            row1 = reinterpret_cast<const f4 *>(S.rows + S.buf + ioff)[q];
+        }
+    }
+    uint4 k_first = words4(S, q, ie, t);
+    asm volatile("" : "+v"(k_first.x), "+v"(k_first.y), "+v"(k_first.z), "+v"(k_first.w));
+
+    const uint32_t prow = st & ST_ROW;
+    const bool alias = (st & ST_ALIAS) != 0u;
+    const f4 *p4 = reinterpret_cast<const f4 *>(S.rows + prow * S.buf + ioff);
+    f4 *x4 = reinterpret_cast<f4 *>(S.rows + (INIT ? 0u : (1u - prow)) * S.buf + ioff);
+    const f4 *xsrc = alias ? p4 : x4;
+    pv[0] = prow ? row1 : row0;
+    xv[0] = alias ? pv[0] : (prow ? row0 : row1);
+
+    const f4 *g4 = reinterpret_cast<const f4 *>(S.rows);
+    // Step m's pBest, position and shift chunks into set b, and its gBest
+    // chunk (known once the key of the previous generation is).
+    auto prefetch_own = [&](uint32_t m, uint32_t b) {
+        const uint32_t c = 8u * m + q;
+        if (FULL_D || c < S.chunks) {
+            sv[b] = s4[c];
+            if constexpr (!INIT) {
+                pv[b] = p4[c];
+                xv[b] = xsrc[c];
+            }
+        }
+    };
+    auto prefetch_g = [&](uint32_t m, uint32_t b) {
+        const uint32_t c = 8u * m + q;
+        if constexpr (!INIT)
+            if (FULL_D || c < S.chunks) gv[b] = g4[c];
+    };
+    if (STEPS > 1) prefetch_own(1, 1);
+    if constexpr (!INIT) {
+        const uint32_t glow = (uint32_t)generation_begin(S, t, blockIdx.x, gkey);
+        const uint32_t gidx = min(glow >> 1, S.n - 1u);
+        g4 = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.stride);
+        prefetch_g(0, 0);
+        if (STEPS > 1) prefetch_g(1, 1);
+    }
+    store_a(0);
+
+    // Select (Eq. 2.1) step m's chunk from set b and write the three bf16
+    // parts of d = x' - s into d-part buffer `db`.
+    auto select_step = [&](uint32_t m, uint32_t b, f4 *db) {
+        const uint32_t c = 8u * m + q;
+        f4 dv = zero4;
+        if (FULL_D || c < S.chunks) {
+            const uint4 k = m == 0 ? k_first : words4(S, c, ie, t);
+            f4 xn;
+            if constexpr (INIT)
+                xn = init4(S, k);
+            else
+                xn = select4<EQ21>(S, k, gv[b], pv[b], xv[b]);
+            x4[c] = xn;
+            if constexpr (FULL_D) {
+                dv = xn - sv[b];
+            } else {
+                const uint32_t j0 = 4u * c;
+                dv.x = (j0 + 0 < S.d) ? xn.x - sv[b].x : 0.f;
+                dv.y = (j0 + 1 < S.d) ? xn.y - sv[b].y : 0.f;
+                dv.z = (j0 + 2 < S.d) ? xn.z - sv[b].z : 0.f;
+                dv.w = (j0 + 3 < S.d) ? xn.w - sv[b].w : 0.f;
+            }
+        }
+        bf16x4 h, md, lo;
+        split3x4(dv, h, md, lo);
+        bf16x4 *dst = reinterpret_cast<bf16x4 *>(db);
+        dst[bsl] = h;
+        dst[bsl + 128u] = md;
+        dst[bsl + 256u] = lo;
+    };
+
+    select_step(0, 0, ldb0);
+
+    f4 acc[2][4];
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r)
+#pragma unroll
+        for (uint32_t pt = 0; pt < 4; ++pt) acc[r][pt] = zero4;
+    const bool mine = NB >= 16 || 2u * wave < (uint32_t)NB;  // this wave owns row blocks
+
+    __syncthreads();  // A block 0 and step 0's d parts are in LDS
+
+#pragma unroll
+    for (uint32_t m = 0; m < STEPS; ++m) {
+        const uint32_t cur = m & 1u;
+        const bool more = m + 1 < STEPS;
+        if (more) load_a(m + 1);
+        if (m + 2 < STEPS) {
+            prefetch_own(m + 2, cur);
+            prefetch_g(m + 2, cur);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (more) select_step(m + 1, cur ^ 1u, cur ? ldb0 : ldb1);
+        if (mine) {
+            const f4 *la = cur ? lda1 : lda0;
+            const f4 *lb = cur ? ldb1 : ldb0;
+            bf16x8 bh[4], bm[4], bl[4];
+#pragma unroll
+            for (uint32_t pt = 0; pt < 4; ++pt) {
+                bh[pt] = __builtin_bit_cast(bf16x8, lb[(pt * 3u + 0u) * 64u + lane]);
+                bm[pt] = __builtin_bit_cast(bf16x8, lb[(pt * 3u + 1u) * 64u + lane]);
+                bl[pt] = __builtin_bit_cast(bf16x8, lb[(pt * 3u + 2u) * 64u + lane]);
+            }
+#pragma unroll
+            for (uint32_t r = 0; r < 2; ++r) {
+                const uint32_t rb = 2u * wave + r;
+                const bf16x8 a1 = __builtin_bit_cast(bf16x8, la[(rb * 3u + 0u) * 64u + lane]);
+                const bf16x8 a2 = __builtin_bit_cast(bf16x8, la[(rb * 3u + 1u) * 64u + lane]);
+                const bf16x8 a3 = __builtin_bit_cast(bf16x8, la[(rb * 3u + 2u) * 64u + lane]);
+                // Smallest products first, four independent accumulators
+                // between two updates of the same one.
+#pragma unroll
+                for (uint32_t pt = 0; pt < 4; ++pt)
+                    acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bl[pt], acc[r][pt], 0, 0, 0);
+#pragma unroll
+                for (uint32_t pt = 0; pt < 4; ++pt)
+                    acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, bh[pt], acc[r][pt], 0, 0, 0);
+#pragma unroll
+                for (uint32_t pt = 0; pt < 4; ++pt)
+                    acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, bm[pt], acc[r][pt], 0, 0, 0);
+#pragma unroll
+                for (uint32_t pt = 0; pt < 4; ++pt)
+                    acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bm[pt], acc[r][pt], 0, 0, 0);
+#pragma unroll
+                for (uint32_t pt = 0; pt < 4; ++pt)
+                    acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, bh[pt], acc[r][pt], 0, 0, 0);
+#pragma unroll
+                for (uint32_t pt = 0; pt < 4; ++pt)
+                    acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bh[pt], acc[r][pt], 0, 0, 0);
+            }
+        }
+        // Step m + 1's A block into the buffer read in step m - 1 (every
+        // wave passed that step's barrier), after this step's MFMAs.
+        __builtin_amdgcn_sched_barrier(0);
+        if (more) store_a(cur ^ 1u);
+        // The LDS writes of this step (A block, d parts) are visible and this
+        // wave's LDS reads of the buffers the next step overwrites are done
+        // before the barrier; loads of later steps stay in flight.
+        // (lgkmcnt is bits 11:8; vmcnt 3:0 and 15:14, expcnt 6:4 at maxima.)
+        __builtin_amdgcn_s_waitcnt(0xC07Fu);  // lgkmcnt(0)
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+    // f = sum_k y_k^2: lane (column l % 16, group l / 16) holds rows
+    // 4 (l / 16) + r of the wave's two row blocks for particle 16 pt + l % 16;
+    // the four lane groups, then the eight waves, meet.
+    float fw[4];
+#pragma unroll
+    for (uint32_t pt = 0; pt < 4; ++pt) {
+        float f = 0.0f;
+#pragma unroll
+        for (uint32_t r = 0; r < 2; ++r) {
+            f += acc[r][pt][0] * acc[r][pt][0];
+            f += acc[r][pt][1] * acc[r][pt][1];
+            f += acc[r][pt][2] * acc[r][pt][2];
+            f += acc[r][pt][3] * acc[r][pt][3];
+        }
+        f += __shfl_xor(f, 16, 64);
+        f += __shfl_xor(f, 32, 64);
+        fw[pt] = f;
+    }
+    const uint32_t lgp = lane >> 4;
+    const float mine_f = lgp == 0 ? fw[0] : lgp == 1 ? fw[1] : lgp == 2 ? fw[2] : fw[3];
+    fpart[wave][16u * lgp + (lane & 15u)] = mine_f;
+    __syncthreads();
+    if (wave != 0) return;
+    float f = 0.0f;
+#pragma unroll
+    for (uint32_t w = 0; w < 8; ++w) f += fpart[w][tid];
+
+    const uint32_t prow_d = std_ & ST_ROW;
+    const bool improved = dvalid && (INIT || improves(f, fpi));
+    uint32_t row = prow_d;
+    float fnew = fpi;
+    if (improved) {
+        row = INIT ? 0u : 1u - prow_d;
+        fnew = f;
+    }
+    if (dvalid) {
+        S.st[idec] = improved ? (row | ST_ALIAS) : row;
+        if (improved) S.fp[idec] = fnew;
+    }
+    const unsigned long long key = dvalid ? gbest_key(fnew, idec, row) : ~0ull;
+    wave_commit(S, t, blockIdx.x, key, improved ? 1u : 0u);
+}
+
 template <int NB, bool FULL_D>
 static void launch_nbf(const SwarmDev &S, uint32_t t, dim3 grid, hipStream_t st)
 {
     const bool eq21 = S.order != 0;
     if (S.a3) {
+#ifdef SSO_DENSE3_FOUR_WAVES
         const dim3 block(256);
         if (t == 0) {
             if (eq21)
@@ -649,6 +951,20 @@ static void launch_nbf(const SwarmDev &S, uint32_t t, dim3 grid, hipStream_t st)
             else
                 hipLaunchKernelGGL((k_dense3<NB, false, false, FULL_D>), grid, block, 0, st, S, t);
         }
+#else
+        const dim3 block(512);
+        if (t == 0) {
+            if (eq21)
+                hipLaunchKernelGGL((k_dense3w<NB, true, true, FULL_D>), grid, block, 0, st, S, t);
+            else
+                hipLaunchKernelGGL((k_dense3w<NB, false, true, FULL_D>), grid, block, 0, st, S, t);
+        } else {
+            if (eq21)
+                hipLaunchKernelGGL((k_dense3w<NB, true, false, FULL_D>), grid, block, 0, st, S, t);
+            else
+                hipLaunchKernelGGL((k_dense3w<NB, false, false, FULL_D>), grid, block, 0, st, S, t);
+        }
+#endif
         return;
     }
     if (t == 0) {
