@@ -48,7 +48,7 @@ KERNEL_SOURCES = {
     "sphere": ("sso_device.hpp", "sso_layout.hpp", "resident.hip"),
     "ripple": ("sso_device.hpp", "sso_layout.hpp", "stream_body.hpp", "gen_stream.hip"),
     "dense": ("sso_device.hpp", "sso_layout.hpp", "gen_dense.hip"),
-    "batch": ("sso_device.hpp", "sso_layout.hpp", "stream_body.hpp", "gen_batch.hip"),
+    "batch": ("sso_device.hpp", "sso_layout.hpp", "stream_body.hpp", "gen_batch.hip", "sso_batch.hip"),
 }
 
 
@@ -414,6 +414,16 @@ def main():
     log(f"gpu: {ms:.3f} ms for {steps} generations, fG={fg:.6g} at t={gen}")
 
     split = wl.kind == "dense" and args.contraction != "f32"
+    f32_line = None
+    if split:
+        # The FP32 contraction the workload names, timed over the same window
+        # beside the default split one.
+        ms32, _, _ = time_gpu(wl, steps, args.warmup, args.engine, "f32")
+        t32 = 2.0 * wl.n * wl.d * wl.d / (ms32 / steps / 1e3) / 1e12
+        f32_line = {"ms_per_step": ms32 / steps, "value": wl.n * wl.d * steps / (ms32 / 1e3),
+                    "achieved_tflops": t32, "frac_of_fp32_matrix_peak": t32 / FP32_MATRIX_PEAK_TFLOPS,
+                    "traffic": measured_traffic(wl, window, wl.name + "/f32")}
+        log(f"gpu, FP32 contraction: {ms32:.3f} ms for {steps} generations")
     if split:
         # The split contraction runs six bf16 products per FP32 product on the
         # bf16 matrix cores: priced at their work and their peak.  The
@@ -480,6 +490,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if f32_line is not None:
+        rec["f32_contraction"] = f32_line
     print(json.dumps(rec), flush=True)
 
 
@@ -699,11 +711,13 @@ def bench_polish(wl, args):
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.contraction == "f32" else "bf16x3",
         "data": "synthetic",
         "config": {"workload": wl.name + "+polish", "objective": wl.kind, "n": wl.n, "d": wl.d,
                    "generations": steps, "polish_every": POLISH_EVERY, "polish_steps": POLISH_STEPS,
-                   "polish_lr": lr},
+                   "polish_lr": lr,
+                   "contraction": "f32" if args.contraction == "f32" else "bf16x3",
+                   "polish_contraction": "f32"},
         "gap": {"target": gap_target, "compared_at": gap,
                 "time_to_target_ms": reached,
                 "time_to_compared_gap_ms": ttg,
@@ -713,7 +727,7 @@ def bench_polish(wl, args):
                 "ms_total": {k: v["ms"] for k, v in runs.items()}},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MATRIX_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / FP32_MATRIX_PEAK_TFLOPS,
-                     "traffic": None},
+                     "traffic": None, "kernel": "polish (FP32 MFMA), timed alone"},
         "polish_rate": {"value": wl.n / (polish_ms / 1e3), "unit": "pBests polished/s"},
         "cpu_baseline": cpu_polish_baseline(wl, lr) if args.cpu_gens != 0 else None,
     }

@@ -288,22 +288,14 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(SwarmDev S, uint32_t t)
 // the matrix cores at the bf16 rate, beside the select's VALU work, instead
 // of on the FP32 path it shares with the VALU.
 //
-// Work split: four waves, one per group of 16 particles, each over the whole
-// inner index.  Step m covers variables [32 m, 32 m + 32): lane l (particle
-// l % 16, lane group g = l / 16) selects chunks 8 m + 2 g and 8 m + 2 g + 1,
-// i.e. variables 32 m + 8 g + j, j = 0..7 -- the eight B-operand elements of
-// the MFMA, whose inner index pairs lane group g, element j of A and B alike.
-// A is packed by the host as [m][row block][part][lane][8 bf16] (A element
-// j of lane l in row block rb is A[16 rb + l % 16][32 m + 8 (l / 16) + j]),
-// so step m is one contiguous 3 x NB KB block, double-buffered in LDS.
-//
-// Pipeline: during step m's MFMAs the wave selects step m + 1's variables
-// (Philox, Eq. 2.1, the split), in the same scheduling region, so that VALU
-// work issues while the matrix cores run; step m + 1's A block and step
-// m + 2's row operands are requested at the start of step m.  With d = dp the
-// select has no branch (see `ie`) and the end of a step waits only for the
-// A block, then meets the other waves at a bare barrier (they share nothing
-// but LDS); other shapes take the plain wait and __syncthreads.
+// Operand layout.  Step m covers variables [32 m, 32 m + 32).  In the
+// 16x16x32 MFMA, lane l supplies A row l % 16 and B column l % 16, and inner
+// elements 8 (l / 16) + j, j = 0..7, for both: B element j of lane l of a
+// particle tile is variable 32 m + 8 (l / 16) + j of particle l % 16, i.e.
+// chunks 8 m + 2 (l / 16) and 8 m + 2 (l / 16) + 1.  A is packed by the host
+// as [m][row block][part][lane][8 bf16] (A element j of lane l in row block
+// rb is A[16 rb + l % 16][32 m + 8 (l / 16) + j]), so step m is one
+// contiguous 3 x NB KB block, double-buffered in LDS.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -360,293 +352,18 @@ void dense_pack_split(const float *a, uint32_t d, uint16_t *out)
         }
 }
 
-// The three bf16 parts of eight FP32 values (d0 then d1).
-__device__ __forceinline__ void split3(f4 d0, f4 d1, bf16x8 &h, bf16x8 &m, bf16x8 &l)
-{
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const float v = j < 4 ? d0[j] : d1[j - 4];
-        const __bf16 v1 = (__bf16)v;
-        const float r1 = v - (float)v1;
-        const __bf16 v2 = (__bf16)r1;
-        h[j] = v1;
-        m[j] = v2;
-        l[j] = (__bf16)(r1 - (float)v2);
-    }
-}
-
-template <int NB, bool EQ21, bool INIT, bool FULL_D>
-__global__ __launch_bounds__(256) void k_dense3(SwarmDev S, uint32_t t)
-{
-    constexpr uint32_t STEPS = NB / 2;                     // 32 variables per step
-    constexpr uint32_t STEP_U = NB * 3u * 64u;             // 16-byte units per step
-    constexpr uint32_t PER = (STEP_U + 255u) / 256u;
-    constexpr bool FULL = STEP_U % 256u == 0;
-    __shared__ f4 lds0[STEP_U];
-    __shared__ f4 lds1[STEP_U];
-
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63u, wave = tid >> 6;
-    const uint32_t pcol = lane & 15u, lg = lane >> 4;
-    const uint32_t i = blockIdx.x * 64u + wave * 16u + pcol;
-    const bool valid = i < S.n;
-    // A lane past the last particle works as a copy of particle n - 1 (same
-    // rows, same words, the same values stored to the same addresses) but
-    // takes no part in the pBest, state and gBest updates: the select then
-    // has no branch, and can be interleaved with the MFMAs.
-    const uint32_t ie = valid ? i : S.n - 1u;
-    const f4 *a_pack = reinterpret_cast<const f4 *>(S.a3);
-
-    unsigned long long gkey = ~0ull;
-    if constexpr (!INIT) gkey = generation_key_load(S, t);
-
-    uint32_t st = ST_ALIAS;  // pBest in row 0, position aliased (generation 0)
-    float fpi = 0.0f;
-    if (!INIT) {
-        st = S.st[ie];
-        fpi = S.fp[ie];
-    }
-    const size_t ioff = (size_t)ie * S.stride;
-    const f4 *s4 = reinterpret_cast<const f4 *>(S.s);
-
-    // Step m's block of A parts straight from global memory into LDS buffer b.
-    auto stage_dma = [&](uint32_t m, uint32_t b) {
-#pragma unroll
-        for (uint32_t r = 0; r < PER; ++r) {
-            const uint32_t q = tid + r * 256u;
-            if (FULL || q < STEP_U)
-                __builtin_amdgcn_global_load_lds(
-                    (const void *)(a_pack + (size_t)m * STEP_U + q),
-                    (__attribute__((address_space(3))) void *)(&(b ? lds1 : lds0)[r * 256u + wave * 64u]), 16, 0, 0);
-        }
-    };
-    if constexpr (INIT) stage_dma(0, 0);
-    const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
-    // Operands of the select, two steps' worth: set m & 1 holds step m's
-    // pBest, position, gBest and shift chunks (u = 0, 1).
-    f4 pv[2][2], xv[2][2], gv[2][2], sv[2][2], row0[2], row1[2];
-#pragma unroll
-    for (uint32_t u = 0; u < 2; ++u) {
-        pv[0][u] = xv[0][u] = gv[0][u] = sv[0][u] = row0[u] = row1[u] = zero4;
-        pv[1][u] = xv[1][u] = gv[1][u] = sv[1][u] = zero4;
-        const uint32_t c = 2u * lg + u;
-        if (FULL_D || c < S.chunks) {
-            sv[0][u] = s4[c];
-            if constexpr (!INIT) {
-                row0[u] = reinterpret_cast<const f4 *>(S.rows + ioff)[c];
-                row1[u] = reinterpret_cast<const f4 *>(S.rows + S.buf + ioff)[c];
-            }
-        }
-    }
-    uint4 k_first[2] = {words4(S, 2u * lg, ie, t), words4(S, 2u * lg + 1u, ie, t)};
-    asm volatile("" : "+v"(k_first[0].x), "+v"(k_first[0].y), "+v"(k_first[0].z), "+v"(k_first[0].w),
-                      "+v"(k_first[1].x), "+v"(k_first[1].y), "+v"(k_first[1].z), "+v"(k_first[1].w));
-
-    const uint32_t prow = st & ST_ROW;
-    const bool alias = (st & ST_ALIAS) != 0u;
-    const f4 *p4 = reinterpret_cast<const f4 *>(S.rows + prow * S.buf + ioff);
-    f4 *x4 = reinterpret_cast<f4 *>(S.rows + (INIT ? 0u : (1u - prow)) * S.buf + ioff);
-    const f4 *xsrc = alias ? p4 : x4;
-#pragma unroll
-    for (uint32_t u = 0; u < 2; ++u) {
-        pv[0][u] = prow ? row1[u] : row0[u];
-        xv[0][u] = alias ? pv[0][u] : (prow ? row0[u] : row1[u]);
-    }
-
-    // Step m's operands into set b.
-    const f4 *g4 = reinterpret_cast<const f4 *>(S.rows);
-    auto prefetch = [&](uint32_t m, uint32_t b) {
-#pragma unroll
-        for (uint32_t u = 0; u < 2; ++u) {
-            const uint32_t c = 8u * m + 2u * lg + u;
-            if (FULL_D || c < S.chunks) {
-                sv[b][u] = s4[c];
-                if constexpr (!INIT) {
-                    pv[b][u] = p4[c];
-                    xv[b][u] = xsrc[c];
-                    gv[b][u] = g4[c];
-                }
-            }
-        }
-    };
-    if constexpr (!INIT) {
-        const uint32_t glow = (uint32_t)generation_begin(S, t, blockIdx.x, gkey);
-        const uint32_t gidx = min(glow >> 1, S.n - 1u);
-        g4 = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf + (size_t)gidx * S.stride);
-        stage_dma(0, 0);
-#pragma unroll
-        for (uint32_t u = 0; u < 2; ++u) {
-            const uint32_t c = 2u * lg + u;
-            if (FULL_D || c < S.chunks) gv[0][u] = g4[c];
-        }
-    }
-    if (STEPS > 1) prefetch(1, 1);
-
-    // Select (Eq. 2.1) step m's chunks from set b, write them, and split
-    // d = x' - s into its three bf16 parts.
-    auto select_step = [&](uint32_t m, uint32_t b, bf16x8 &h, bf16x8 &mid, bf16x8 &lo) {
-        f4 dv[2] = {zero4, zero4};
-#pragma unroll
-        for (uint32_t u = 0; u < 2; ++u) {
-            const uint32_t c = 8u * m + 2u * lg + u;
-            if (FULL_D || c < S.chunks) {
-                const uint4 k = m == 0 ? k_first[u] : words4(S, c, ie, t);
-                f4 xn;
-                if constexpr (INIT)
-                    xn = init4(S, k);
-                else
-                    xn = select4<EQ21>(S, k, gv[b][u], pv[b][u], xv[b][u]);
-                x4[c] = xn;
-                if constexpr (FULL_D) {
-                    dv[u] = xn - sv[b][u];
-                } else {
-                    const uint32_t j0 = 4u * c;
-                    dv[u].x = (j0 + 0 < S.d) ? xn.x - sv[b][u].x : 0.f;
-                    dv[u].y = (j0 + 1 < S.d) ? xn.y - sv[b][u].y : 0.f;
-                    dv[u].z = (j0 + 2 < S.d) ? xn.z - sv[b][u].z : 0.f;
-                    dv[u].w = (j0 + 3 < S.d) ? xn.w - sv[b][u].w : 0.f;
-                }
-            }
-        }
-        split3(dv[0], dv[1], h, mid, lo);
-    };
-
-    bf16x8 dh, dm, dl;
-    select_step(0, 0, dh, dm, dl);
-
-    f4 acc[NB];
-#pragma unroll
-    for (uint32_t rb = 0; rb < NB; ++rb) acc[rb] = zero4;
-
-    __builtin_amdgcn_s_waitcnt(0);  // buffer 0 and step 1's operands have landed
-    __syncthreads();
-
-    // Step m: the MFMAs of step m (operands selected one step earlier) and
-    // the select of step m + 1 in one region, so that the VALU work issues
-    // while the matrix cores run; step m + 1's A block and step m + 2's
-    // operands are requested first.
-#pragma unroll
-    for (uint32_t m = 0; m < STEPS; ++m) {
-        const uint32_t cur = m & 1u;
-        const bool more = m + 1 < STEPS;
-        if (more) stage_dma(m + 1, cur ^ 1u);
-        // The copy goes out before the loads below (the wait at the end of
-        // the step counts on that order).
-        __builtin_amdgcn_sched_barrier(0);
-        if (m + 2 < STEPS) prefetch(m + 2, cur);
-        __builtin_amdgcn_sched_barrier(0);
-        const f4 *la = cur ? lds1 : lds0;
-        bf16x8 nh = dh, nm = dm, nl = dl;
-        if (more) select_step(m + 1, cur ^ 1u, nh, nm, nl);
-#pragma unroll
-        for (uint32_t r0 = 0; r0 < NB; r0 += 4) {
-            bf16x8 a1[4], a2[4], a3[4];
-#pragma unroll
-            for (uint32_t q = 0; q < 4 && r0 + q < NB; ++q) {
-                a1[q] = __builtin_bit_cast(bf16x8, la[((r0 + q) * 3u + 0u) * 64u + lane]);
-                a2[q] = __builtin_bit_cast(bf16x8, la[((r0 + q) * 3u + 1u) * 64u + lane]);
-                a3[q] = __builtin_bit_cast(bf16x8, la[((r0 + q) * 3u + 2u) * 64u + lane]);
-            }
-            // Smallest products first; four independent accumulators between
-            // two updates of the same one.
-#pragma unroll
-            for (uint32_t q = 0; q < 4 && r0 + q < NB; ++q)
-                acc[r0 + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[q], dl, acc[r0 + q], 0, 0, 0);
-#pragma unroll
-            for (uint32_t q = 0; q < 4 && r0 + q < NB; ++q)
-                acc[r0 + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[q], dh, acc[r0 + q], 0, 0, 0);
-#pragma unroll
-            for (uint32_t q = 0; q < 4 && r0 + q < NB; ++q)
-                acc[r0 + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[q], dm, acc[r0 + q], 0, 0, 0);
-#pragma unroll
-            for (uint32_t q = 0; q < 4 && r0 + q < NB; ++q)
-                acc[r0 + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[q], dm, acc[r0 + q], 0, 0, 0);
-#pragma unroll
-            for (uint32_t q = 0; q < 4 && r0 + q < NB; ++q)
-                acc[r0 + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[q], dh, acc[r0 + q], 0, 0, 0);
-#pragma unroll
-            for (uint32_t q = 0; q < 4 && r0 + q < NB; ++q)
-                acc[r0 + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[q], dh, acc[r0 + q], 0, 0, 0);
-        }
-        if (more) {
-            // The select and the MFMAs share one branch-free region, which
-            // the compiler's scheduler interleaves by itself (fixed patterns
-            // of MFMA, VALU and LDS-read groups measured slower).
-            if constexpr (FULL_D && !INIT) {
-                // Step m + 1's A block has landed once at most the eight
-                // operand loads of step m + 2 (issued after the copy) are
-                // outstanding: loads complete in issue order, and counting
-                // the row stores, which may complete in any order relative to
-                // them, could only make the wait longer (vmcnt is bits 3:0
-                // and 15:14; expcnt 6:4 and lgkmcnt 11:8 left at their maxima).
-                if (m + 2 < STEPS)
-                    __builtin_amdgcn_s_waitcnt(8u | 0x70u | 0xf00u);  // vmcnt(8)
-                else
-                    __builtin_amdgcn_s_waitcnt(0u | 0x70u | 0xf00u);  // vmcnt(0)
-            } else {
-                __builtin_amdgcn_s_waitcnt(0);  // step m + 1's A block and operands have landed
-            }
-        }
-        if constexpr (FULL_D && !INIT) {
-            // The waves share only the LDS buffers, so the barrier needs no
-            // wait on global memory beyond the one above (a full
-            // __syncthreads would wait for step m + 2's operands and the
-            // row stores as well).  The empty asm keeps the compiler's LDS
-            // accesses on their side of it.
-            asm volatile("" ::: "memory");
-            __builtin_amdgcn_s_barrier();
-            asm volatile("" ::: "memory");
-        } else {
-            __syncthreads();
-        }
-        dh = nh;
-        dm = nm;
-        dl = nl;
-    }
-
-    // f = sum_k y_k^2: this lane holds rows 4 lg + r of every row block of
-    // particle pcol; the four lane groups then meet.
-    float f = 0.0f;
-#pragma unroll
-    for (uint32_t rb = 0; rb < NB; ++rb) {
-        f += acc[rb][0] * acc[rb][0];
-        f += acc[rb][1] * acc[rb][1];
-        f += acc[rb][2] * acc[rb][2];
-        f += acc[rb][3] * acc[rb][3];
-    }
-    f += __shfl_xor(f, 16, 64);
-    f += __shfl_xor(f, 32, 64);
-
-    const bool improved = valid && (INIT || improves(f, fpi));
-    uint32_t row = prow;
-    float fnew = fpi;
-    if (improved) {
-        row = INIT ? 0u : 1u - prow;
-        fnew = f;
-    }
-    if (valid && lg == 0) {
-        S.st[i] = improved ? (row | ST_ALIAS) : row;
-        if (improved) S.fp[i] = fnew;
-    }
-    const unsigned long long key = valid ? gbest_key(fnew, i, row) : ~0ull;
-    wave_commit(S, t, blockIdx.x * 4u + wave, key, (improved && lg == 0) ? 1u : 0u);
-}
-
-// ---------------------------------------------------------------------------
-// Split contraction, eight waves (the default form of the split kernel).
-//
-// Same arithmetic as k_dense3 (three exact bf16 parts per FP32 operand, the
-// six part products above 2^-24 relative weight, FP32 accumulation), with
-// the 64 particles of a workgroup spread over eight waves, two per SIMD, so
-// that one wave's matrix-core work runs while the other selects or waits.
+// The generation kernel.  The 64 particles of a workgroup are spread over
+// eight waves, two per SIMD, so that one wave's matrix-core work runs while
+// the other selects or waits.
 //   Select: thread (particle pl = tid / 8, q = tid % 8) selects chunk
 //   8 m + q of its particle in step m (Eq. 2.1), writes it, and writes the
-//   three bf16 parts of d = x' - s into LDS in the B-operand layout of the MFMA: tile pl / 16,
-//   lane (pl % 16) + 16 (q / 2), elements 4 (q % 2) .. 4 (q % 2) + 3.
+//   three bf16 parts of d = x' - s into LDS in the B-operand layout: tile
+//   pl / 16, lane (pl % 16) + 16 (q / 2), elements 4 (q % 2) .. 4 (q % 2) + 3.
 //   Contract: wave w owns row blocks 2 w and 2 w + 1 of A for all four tiles
 //   of 16 particles: per step it reads 6 A operands (its row blocks, three
 //   parts) and 12 B operands (four tiles, three parts) from LDS for 48
-//   MFMAs, against 48 A and no B reads for 96 MFMAs per wave in k_dense3.
+//   MFMAs (a wave owning all 256 rows of 16 particles would read 48 A
+//   operands for 96).
 //   Fitness: each wave's partial sum of y_k^2 over its 32 rows per particle
 //   meets the others' in LDS, added in wave order.
 // One barrier per step: step m + 1's A block and d parts are written during
@@ -654,7 +371,6 @@ __global__ __launch_bounds__(256) void k_dense3(SwarmDev S, uint32_t t)
 // registers (plain loads, then LDS stores): with a global-to-LDS copy in
 // flight the compiler waits for every outstanding load before it uses any
 // loaded register, which would drain the prefetch of later steps each step.
-// ---------------------------------------------------------------------------
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 // The three bf16 parts of four FP32 values.
@@ -673,7 +389,7 @@ __device__ __forceinline__ void split3x4(f4 d, bf16x4 &h, bf16x4 &m, bf16x4 &l)
 }
 
 template <int NB, bool EQ21, bool INIT, bool FULL_D>
-__global__ __launch_bounds__(512) void k_dense3w(SwarmDev S, uint32_t t)
+__global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
 {
     constexpr uint32_t STEPS = NB / 2;              // 32 variables per step
     constexpr uint32_t STEP_U = NB * 3u * 64u;      // 16-byte units of A per step
@@ -938,8 +654,7 @@ static void launch_nbf(const SwarmDev &S, uint32_t t, dim3 grid, hipStream_t st)
 {
     const bool eq21 = S.order != 0;
     if (S.a3) {
-#ifdef SSO_DENSE3_FOUR_WAVES
-        const dim3 block(256);
+        const dim3 block(512);
         if (t == 0) {
             if (eq21)
                 hipLaunchKernelGGL((k_dense3<NB, true, true, FULL_D>), grid, block, 0, st, S, t);
@@ -951,20 +666,6 @@ static void launch_nbf(const SwarmDev &S, uint32_t t, dim3 grid, hipStream_t st)
             else
                 hipLaunchKernelGGL((k_dense3<NB, false, false, FULL_D>), grid, block, 0, st, S, t);
         }
-#else
-        const dim3 block(512);
-        if (t == 0) {
-            if (eq21)
-                hipLaunchKernelGGL((k_dense3w<NB, true, true, FULL_D>), grid, block, 0, st, S, t);
-            else
-                hipLaunchKernelGGL((k_dense3w<NB, false, true, FULL_D>), grid, block, 0, st, S, t);
-        } else {
-            if (eq21)
-                hipLaunchKernelGGL((k_dense3w<NB, true, false, FULL_D>), grid, block, 0, st, S, t);
-            else
-                hipLaunchKernelGGL((k_dense3w<NB, false, false, FULL_D>), grid, block, 0, st, S, t);
-        }
-#endif
         return;
     }
     if (t == 0) {
