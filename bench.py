@@ -117,7 +117,7 @@ def time_gpu(wl, steps, warmup, engine, contraction="auto"):
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
     g, fg, gidx, gen = sw.best()
-    return ms, fg, gen
+    return ms, fg, gen, sw.mapping()
 
 
 def time_gpu_batch(swarms, steps, tune_gens):
@@ -127,8 +127,9 @@ def time_gpu_batch(swarms, steps, tune_gens):
 
     stream = torch.cuda.Stream()
     batch = Batch(swarms, stream=stream)
-    cpl, tune_ms = batch.tune(tune_gens)
-    log(f"mapping rule {cpl} chunks per lane; tuner ms per {tune_gens} generations: {tune_ms}")
+    cpl, waves, tune_ms = batch.tune(tune_gens)
+    log(f"mapping rule {cpl} chunks per lane, {waves} waves per workgroup; tuner ms per "
+        f"{tune_gens} generations: {tune_ms}")
     stream.synchronize()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
@@ -140,8 +141,8 @@ def time_gpu_batch(swarms, steps, tune_gens):
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
     f, gi, im, gen = batch.results()
-    _, lanes, tiles = batch.mapping()
-    return ms, f, gen, cpl, tiles, lanes
+    _, _, lanes, tiles = batch.mapping()
+    return ms, f, gen, (cpl, waves), tiles, lanes
 
 
 def time_gpu_separate(swarms, steps, lanes):
@@ -406,7 +407,8 @@ def main():
     window = timed_window(wl, steps)
     log(f"workload {wl.name}: N={wl.n} D={wl.d} steps={steps} warmup={args.warmup}, "
         f"timed generations {window[0]}..{window[1]}")
-    ms, fg, gen = time_gpu(wl, steps, args.warmup, args.engine, args.contraction)
+    ms, fg, gen, (engine, storage, lanes) = time_gpu(wl, steps, args.warmup, args.engine,
+                                                     args.contraction)
     sec = ms / 1e3
     updates = wl.n * wl.d * steps
     value = updates / sec
@@ -418,7 +420,7 @@ def main():
     if split:
         # The FP32 contraction the workload names, timed over the same window
         # beside the default split one.
-        ms32, _, _ = time_gpu(wl, steps, args.warmup, args.engine, "f32")
+        ms32, _, _, _ = time_gpu(wl, steps, args.warmup, args.engine, "f32")
         t32 = 2.0 * wl.n * wl.d * wl.d / (ms32 / steps / 1e3) / 1e12
         f32_line = {"ms_per_step": ms32 / steps, "value": wl.n * wl.d * steps / (ms32 / 1e3),
                     "achieved_tflops": t32, "frac_of_fp32_matrix_peak": t32 / FP32_MATRIX_PEAK_TFLOPS,
@@ -484,9 +486,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "objective": wl.kind, "n": wl.n, "d": wl.d,
                    "generations": max(steps, wl.generations),
-                   "timed_generations": list(window), "engine": args.engine,
+                   "timed_generations": list(window), "engine": engine,
                    **({"contraction": "f32" if args.contraction == "f32" else "bf16x3"}
-                      if wl.kind == "dense" else {})},
+                      if wl.kind == "dense" else {"row_storage": storage,
+                                                  "lanes_per_particle": lanes})},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -504,11 +507,11 @@ PAPER_QUALITY = {"f1": (41.0156, 5.3095, 28.5125), "f4": (1103.9103, 134.5448, 7
                  "f5": (220.6183, 16.2710, 189.2935)}
 
 
-def paper_swarm(pw, seed=None, stream=None):
+def paper_swarm(pw, seed=None, stream=None, engine="auto"):
     from paper_2110_01470_amd.binding import Swarm
 
     return Swarm(pw.n, pw.d, pw.kind, pw.lo, pw.hi, pw.cg, pw.cp, pw.cw,
-                 pw.seed if seed is None else seed, None, order=1, engine="stream",
+                 pw.seed if seed is None else seed, None, order=1, engine=engine,
                  stream=stream)
 
 
@@ -524,7 +527,7 @@ def bench_paper(pw, args):
     steps = args.steps if args.steps is not None else pw.generations
     stream = torch.cuda.Stream()
     for _ in range(max(1, args.warmup // 10)):  # warm-up whole runs
-        sw = paper_swarm(pw, stream=stream)
+        sw = paper_swarm(pw, stream=stream, engine=args.engine)
         sw.run(steps)
         sw.best()
         sw.close()
@@ -532,14 +535,14 @@ def bench_paper(pw, args):
     for _ in range(5):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sw = paper_swarm(pw, stream=stream)
+        sw = paper_swarm(pw, stream=stream, engine=args.engine)
         sw.run(steps)
         g, fg, gidx, gen = sw.best()
         walls.append(time.perf_counter() - t0)
         sw.close()
     wall = float(np.median(walls))
     # The generations alone, with HIP events.
-    sw = paper_swarm(pw, stream=stream)
+    sw = paper_swarm(pw, stream=stream, engine=args.engine)
     stream.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -547,6 +550,7 @@ def bench_paper(pw, args):
     e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1)
+    engine, storage, lanes = sw.mapping()
     ms_per_step = ms / steps
     updates = pw.n * pw.d * steps
     log(f"{pw.name}: whole run {wall * 1e3:.2f} ms (median of 5), generations {ms:.2f} ms, "
@@ -590,14 +594,19 @@ def bench_paper(pw, args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": pw.name, "objective": pw.kind, "n": pw.n, "d": pw.d,
-                   "generations": steps, "box": [pw.lo, pw.hi], "order": "eq21",
+                   "generations": steps, "box": [pw.lo, pw.hi], "order": "eq21", "engine": engine,
+                   "row_storage": storage, "lanes_per_particle": lanes,
                    "cw_cp_cg": [pw.cw, pw.cp, pw.cg]},
         "updates_per_s": updates / (ms / 1e3),
         "final_fG": fg,
         "paper_context": ({"seconds": paper_s, "hardware": "GTX 1080", "source": "Table 3.10"}
                           if paper_s else None),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "note": "algorithmic rate only: a swarm this small is bound by each "
+                             "generation's dependent chain (one workgroup's ALU work with the "
+                             "resident engine, launch and memory latency with the stream one), "
+                             "not by HBM"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
@@ -615,7 +624,7 @@ def paper_quality(workloads, args):
         pw = workloads[f"paper_f{k}_n100_d50"]
         finals = []
         for seed in range(1001, 1021):
-            sw = paper_swarm(pw, seed=seed, stream=stream)
+            sw = paper_swarm(pw, seed=seed, stream=stream, engine=args.engine)
             sw.run(pw.generations)
             finals.append(sw.best()[1])
             sw.close()
@@ -765,13 +774,13 @@ def cpu_polish_baseline(wl, lr, sample=1024):
 def bench_batch(bw, args):
     """The batched workload: every swarm advances `steps` generations; a step
     is one generation of all swarms (one launch, replayed from graphs)."""
-    from paper_2110_01470_amd.binding import TUNE_CANDIDATES
+    from paper_2110_01470_amd.binding import TUNE_CANDIDATES, TUNE_WAVES
 
     steps = args.steps if args.steps is not None else bw.generations
     swarms = bw.swarms()
     total = sum(sw["n"] * sw["d"] for sw in swarms)
     log(f"workload {bw.name}: {bw.count} swarms, {total} variables, steps={steps}")
-    ms, fb, gen, cpl, tiles, lanes = time_gpu_batch(swarms, steps, args.tune_gens)
+    ms, fb, gen, (cpl, waves), tiles, lanes = time_gpu_batch(swarms, steps, args.tune_gens)
     sec = ms / 1e3
     ms_per_step = ms / steps
     log(f"gpu: {ms:.3f} ms for {steps} generations, best fG over swarms={float(fb.min()):.6g} "
@@ -812,7 +821,8 @@ def bench_batch(bw, args):
         "unit": "particle-var updates/s",
         "n_gpus": 1,
         "steps": steps,
-        "warmup": len(TUNE_CANDIDATES) * args.tune_gens,  # the tuner's timed generations
+        # the tuner's timed generations
+        "warmup": len(TUNE_CANDIDATES) * len(TUNE_WAVES) * args.tune_gens,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -821,7 +831,8 @@ def bench_batch(bw, args):
         "data": "synthetic",
         "config": {"workload": bw.name, "objective": bw.kind, "swarms": bw.count,
                    "variables": total, "generations": steps, "mapping_rule": cpl,
-                   "workgroups_per_launch": tiles, "graph_block": 50},
+                   "waves_per_workgroup": waves, "workgroups_per_launch": tiles,
+                   "graph_block": 50},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

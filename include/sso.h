@@ -244,6 +244,14 @@ void sso_destroy(sso_ctx *ctx);
 int sso_run_static(const sso_config *cfg, uint32_t generations, void *hip_stream,
                    float *dev_g, float *dev_f, uint32_t *dev_idx);
 
+/* What the context resolved its config to: *engine_out SSO_ENGINE_STREAM or
+ * SSO_ENGINE_RESIDENT (AUTO takes RESIDENT for a separable swarm that fits
+ * one workgroup, and for Table 3.2's functions while N times the lanes per
+ * particle is at most 3328; STREAM otherwise), *storage_out SSO_STORAGE_F32
+ * or SSO_STORAGE_U24, *lanes_out the lanes per particle.  Any pointer may
+ * be NULL.  Host only; SSO_E_INVAL for a NULL ctx. */
+int sso_get_mapping(const sso_ctx *ctx, int *engine_out, int *storage_out, uint32_t *lanes_out);
+
 /* Static text for an SSO_* code. */
 const char *sso_strerror(int code);
 
@@ -262,8 +270,9 @@ const char *sso_last_error(const sso_ctx *ctx);
  * (SPHERE or RIPPLE), the same order and the same resolved storage; engine
  * must be AUTO or STREAM; d <= 1024.  The lanes per particle of each swarm
  * come from a mapping rule (a target number of 4-variable chunks per lane,
- * "cpl") unless its config fixes `lanes`; sso_batch_tune() picks the rule by
- * timing.  Ownership, synchronisation and return codes are as for the
+ * "cpl") unless its config fixes `lanes`; a generation launch runs
+ * workgroups of 4 or 8 waves (4 until tuned); sso_batch_tune() picks the
+ * rule and the workgroup size by timing.  Ownership, synchronisation and return codes are as for the
  * one-swarm calls; all swarms share the generation count.
  * ------------------------------------------------------------------------ */
 typedef struct sso_batch sso_batch;
@@ -281,17 +290,32 @@ int sso_batch_init(const sso_config *cfgs, uint32_t count, void *dev_workspace,
 int sso_batch_run(sso_batch *b, uint32_t generations);
 
 /* Autotuner.  Only right after sso_batch_init (no generations run yet):
- * for each candidate rule cpl in {1, 2, 4, 8, 16} re-initialises the batch
- * and times `generations` generations with HIP events; keeps the fastest
- * rule and re-initialises under it, so the batch is again at generation 0.
- * *cpl_out (may be NULL) receives the rule, ms_out[5] (may be NULL) the
- * measured milliseconds per candidate.  Synchronises. */
-int sso_batch_tune(sso_batch *b, uint32_t generations, uint32_t *cpl_out, float *ms_out);
+ * for each candidate mapping -- rule cpl in {1, 2, 4, 8, 16} times
+ * workgroups of 4 or 8 waves -- re-initialises the batch and times
+ * `generations` generations with HIP events; keeps the fastest and
+ * re-initialises under it, so the batch is again at generation 0.  The
+ * mapping changes only the launch shape, never a swarm's results (a swarm's
+ * lanes per particle come from the rule; its particles fall into workgroups
+ * of 4 or 8 waves).  *cpl_out and *waves_out (may be NULL) receive the
+ * choice, ms_out[10] (may be NULL) the milliseconds of candidate
+ * 2 * r + w (r indexes the rules above in order, w = 0 for 4 waves, 1 for
+ * 8).  Synchronises. */
+int sso_batch_tune(sso_batch *b, uint32_t generations, uint32_t *cpl_out, uint32_t *waves_out,
+                   float *ms_out);
 
-/* The current mapping: *cpl_out the rule, lanes_out[count] each swarm's
- * lanes per particle, *tiles_out the workgroups per generation launch.
- * Any pointer may be NULL. */
-int sso_batch_mapping(sso_batch *b, uint32_t *cpl_out, uint32_t *lanes_out, uint32_t *tiles_out);
+/* Sets the mapping to rule cpl (1..64 chunks per lane) and workgroups of
+ * `waves` waves (4 or 8) without timing, e.g. one an earlier
+ * sso_batch_tune() chose; only at generation 0 (no generations run), and
+ * re-initialises the batch (generation 0 again).  SSO_E_INVAL for another
+ * rule or size, SSO_E_STATE after generations.  Enqueued on the batch's
+ * stream. */
+int sso_batch_set_mapping(sso_batch *b, uint32_t cpl, uint32_t waves);
+
+/* The current mapping: *cpl_out the rule, *waves_out the waves per
+ * workgroup, lanes_out[count] each swarm's lanes per particle, *tiles_out
+ * the workgroups per generation launch.  Any pointer may be NULL. */
+int sso_batch_mapping(sso_batch *b, uint32_t *cpl_out, uint32_t *waves_out, uint32_t *lanes_out,
+                      uint32_t *tiles_out);
 
 /* Synchronise, then for every swarm k: f_out[k] its gBest fitness (FP32),
  * idx_out[k] the gBest particle index, improved_out[k] the pBests replaced in

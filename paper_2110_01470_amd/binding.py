@@ -86,11 +86,13 @@ def load():
         "sso_run_static": (ctypes.c_int, [cfgp, u32, P, P, P, P]),
         "sso_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sso_last_error": (ctypes.c_char_p, [P]),
+        "sso_get_mapping": (ctypes.c_int, [P, P, P, P]),
         "sso_batch_workspace_bytes": (ctypes.c_size_t, [cfgp, u32]),
         "sso_batch_init": (ctypes.c_int, [cfgp, u32, P, ctypes.c_size_t, P, ctypes.POINTER(P)]),
         "sso_batch_run": (ctypes.c_int, [P, u32]),
-        "sso_batch_tune": (ctypes.c_int, [P, u32, P, P]),
-        "sso_batch_mapping": (ctypes.c_int, [P, P, P, P]),
+        "sso_batch_tune": (ctypes.c_int, [P, u32, P, P, P]),
+        "sso_batch_set_mapping": (ctypes.c_int, [P, u32, u32]),
+        "sso_batch_mapping": (ctypes.c_int, [P, P, P, P, P]),
         "sso_batch_get_results": (ctypes.c_int, [P, P, P, P, P]),
         "sso_batch_get_best": (ctypes.c_int, [P, u32, P, P, P]),
         "sso_batch_get_state": (ctypes.c_int, [P, u32, P, P, P, P]),
@@ -223,6 +225,18 @@ class Swarm:
         self._check(self._lib.sso_run(self._ctx, generations))
         return self
 
+    def mapping(self):
+        """(engine, row storage, lanes per particle) the config resolved to,
+        as names ("stream"/"resident", "f32"/"u24")."""
+        eng = ctypes.c_int()
+        sto = ctypes.c_int()
+        lanes = ctypes.c_uint32()
+        self._check(self._lib.sso_get_mapping(self._ctx, ctypes.byref(eng), ctypes.byref(sto),
+                                              ctypes.byref(lanes)))
+        names = {v: k for k, v in ENGINE.items()}
+        stores = {v: k for k, v in STORAGE.items()}
+        return names[eng.value], stores[sto.value], int(lanes.value)
+
     def best(self):
         """(g [d], fG, gidx, generations done)."""
         g = np.zeros(self.d, np.float32)
@@ -321,8 +335,10 @@ class Swarm:
         return out.cpu().numpy().view(np.uint32).reshape(self.n, self.d)
 
 
-# Candidate mapping rules of sso_batch_tune (target chunks per lane).
+# Candidate mapping rules of sso_batch_tune (target chunks per lane) and
+# workgroup sizes (waves); it times every pair.
 TUNE_CANDIDATES = (1, 2, 4, 8, 16)
+TUNE_WAVES = (4, 8)
 
 
 class Batch:
@@ -387,20 +403,30 @@ class Batch:
         return self.run(1)
 
     def tune(self, generations):
-        """(chosen rule, {rule: milliseconds})."""
+        """(chosen rule, chosen waves per workgroup, {(rule, waves): milliseconds})."""
         cpl = ctypes.c_uint32()
-        ms = np.zeros(len(TUNE_CANDIDATES), np.float32)
-        self._check(self._lib.sso_batch_tune(self._ctx, generations, ctypes.byref(cpl), _ptr(ms)))
-        return int(cpl.value), dict(zip(TUNE_CANDIDATES, ms.tolist()))
+        waves = ctypes.c_uint32()
+        ms = np.zeros(len(TUNE_CANDIDATES) * len(TUNE_WAVES), np.float32)
+        self._check(self._lib.sso_batch_tune(self._ctx, generations, ctypes.byref(cpl),
+                                             ctypes.byref(waves), _ptr(ms)))
+        keys = [(r, w) for r in TUNE_CANDIDATES for w in TUNE_WAVES]
+        return int(cpl.value), int(waves.value), dict(zip(keys, ms.tolist()))
+
+    def set_mapping(self, rule, waves):
+        """Use mapping rule `rule` and workgroups of `waves` waves; back to
+        generation 0."""
+        self._check(self._lib.sso_batch_set_mapping(self._ctx, rule, waves))
 
     def mapping(self):
-        """(rule, lanes per particle of every swarm, workgroups per launch)."""
+        """(rule, waves per workgroup, lanes per particle of every swarm,
+        workgroups per launch)."""
         cpl = ctypes.c_uint32()
+        waves = ctypes.c_uint32()
         tiles = ctypes.c_uint32()
         lanes = np.zeros(self.count, np.uint32)
-        self._check(self._lib.sso_batch_mapping(self._ctx, ctypes.byref(cpl), _ptr(lanes),
-                                                ctypes.byref(tiles)))
-        return int(cpl.value), lanes, int(tiles.value)
+        self._check(self._lib.sso_batch_mapping(self._ctx, ctypes.byref(cpl), ctypes.byref(waves),
+                                                _ptr(lanes), ctypes.byref(tiles)))
+        return int(cpl.value), int(waves.value), lanes, int(tiles.value)
 
     def results(self):
         """(fG [count], gidx [count], improved [count], generations done)."""

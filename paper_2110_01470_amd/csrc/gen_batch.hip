@@ -14,17 +14,17 @@
 
 namespace sso {
 
-template <int KIND, bool EQ21, bool INIT, class Store>
-__global__ __launch_bounds__(64 * kWaves) void k_batch(BatchDev B, uint32_t j)
+template <int KIND, bool EQ21, bool INIT, class Store, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_batch(BatchDev B, uint32_t j)
 {
     const uint32_t sw = B.tiles[2u * blockIdx.x];
     const uint32_t blk = B.tiles[2u * blockIdx.x + 1u];
     const SwarmDev S = B.table[sw];
     const uint32_t t = INIT ? 0u : *B.tbase + j;
     if (S.d & 3u)
-        stream_body<KIND, 0, EQ21, INIT, true, true, Store, false>(S, t, blk, S.lanes);
+        stream_body<KIND, 0, EQ21, INIT, true, true, Store, false, WAVES>(S, t, blk, S.lanes);
     else
-        stream_body<KIND, 0, EQ21, INIT, false, true, Store, false>(S, t, blk, S.lanes);
+        stream_body<KIND, 0, EQ21, INIT, false, true, Store, false, WAVES>(S, t, blk, S.lanes);
 }
 
 // Trace ring and sub-slot groups of swarm blockIdx.x to "nothing yet".
@@ -68,18 +68,25 @@ __global__ void k_batch_collect(BatchDev B, uint32_t t)
 
 namespace {
 
-template <int KIND, bool EQ21, bool INIT>
-const void *kernel_for_storage(int storage)
+template <int KIND, bool EQ21, bool INIT, class Store>
+const void *kernel_for_waves(uint32_t waves)
 {
-    return storage == STORE_U24 ? reinterpret_cast<const void *>(&k_batch<KIND, EQ21, INIT, StoreU24>)
-                                : reinterpret_cast<const void *>(&k_batch<KIND, EQ21, INIT, StoreF32>);
+    if (waves == 4u) return reinterpret_cast<const void *>(&k_batch<KIND, EQ21, INIT, Store, 4>);
+    if (waves == 8u) return reinterpret_cast<const void *>(&k_batch<KIND, EQ21, INIT, Store, 8>);
+    return nullptr;
+}
+
+template <int KIND, bool EQ21, bool INIT>
+const void *kernel_for_storage(const BatchDev &B)
+{
+    return B.storage == STORE_U24 ? kernel_for_waves<KIND, EQ21, INIT, StoreU24>(B.waves)
+                                  : kernel_for_waves<KIND, EQ21, INIT, StoreF32>(B.waves);
 }
 
 template <int KIND, bool INIT>
 const void *kernel_for_order(const BatchDev &B)
 {
-    return B.order ? kernel_for_storage<KIND, true, INIT>(B.storage)
-                   : kernel_for_storage<KIND, false, INIT>(B.storage);
+    return B.order ? kernel_for_storage<KIND, true, INIT>(B) : kernel_for_storage<KIND, false, INIT>(B);
 }
 
 template <bool INIT>
@@ -95,7 +102,7 @@ int launch_gen(const BatchDev &B, const void *fn, uint32_t j, hipStream_t st)
     if (!fn) return (int)hipErrorInvalidValue;
     BatchDev b = B;
     void *args[] = {&b, &j};
-    return (int)hipLaunchKernel(fn, dim3(B.ntiles), dim3(64 * kWaves), args, B.lds, st);
+    return (int)hipLaunchKernel(fn, dim3(B.ntiles), dim3(64 * B.waves), args, B.lds, st);
 }
 
 }  // namespace
@@ -156,7 +163,7 @@ int batch_graph(const BatchDev &B, uint32_t k, void **graph_out)
         if (j <= k) {
             p.func = const_cast<void *>(fn);
             p.gridDim = dim3(B.ntiles);
-            p.blockDim = dim3(64 * kWaves);
+            p.blockDim = dim3(64 * B.waves);
             p.sharedMemBytes = B.lds;
             p.kernelParams = gen_args;
         } else {

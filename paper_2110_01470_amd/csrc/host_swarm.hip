@@ -82,11 +82,29 @@ bool values_to_row(const SwarmDev &S, const float *in, uint32_t *row)
     return true;
 }
 
-bool resident_possible(const sso_config &c) { return resident_fits(c.n, c.d, c.kind); }
+bool resident_possible(const sso_config &c)
+{
+    if (!resident_fits(c.n, c.d, c.kind)) return false;
+    // Table 3.2's functions: one workgroup's time grows with the particles
+    // each SIMD walks (about 0.29 us per wave of them, 1.08 us with one),
+    // a launch per generation costs about 4.4 us whatever N; measured on
+    // Rosenbrock, D = 50, the two meet near 13 waves per SIMD (N = 208).
+    return !is_paper_kind(c.kind) ||
+           (uint64_t)c.n * stream_lanes(c.d, STORE_F32) <= kResidentPaperAutoLanes;
+}
 
 }  // namespace
 
 size_t align256(size_t x) { return (x + 255u) & ~(size_t)255u; }
+
+uint32_t stream_lanes(uint32_t d, int storage)
+{
+    const uint32_t chunks = (d + 3) / 4;
+    const uint32_t cap = storage == STORE_U24 ? 32u : 64u;
+    uint32_t L = 8;
+    while (L < chunks && L < cap) L <<= 1;
+    return L;
+}
 
 uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 
@@ -124,8 +142,6 @@ int validate_msg(const sso_config *c, const char **why)
     if ((c->kind < SSO_OBJ_SPHERE || c->kind > SSO_OBJ_DENSE) && !paper)
         return bad(SSO_E_INVAL, "unknown objective kind");
     if (paper && c->d > 1024) return bad(SSO_E_UNSUPPORTED, "the Table 3.2 functions support d <= 1024");
-    if (paper && c->engine == SSO_ENGINE_RESIDENT)
-        return bad(SSO_E_UNSUPPORTED, "the Table 3.2 functions run on the STREAM engine");
     if (c->kind == SSO_OBJ_DENSE && c->d > kDenseMaxD) return bad(SSO_E_UNSUPPORTED, "dense objective supports d <= 256");
     if (c->order != SSO_ORDER_GPS && c->order != SSO_ORDER_EQ21) return bad(SSO_E_INVAL, "unknown interval order");
     if (c->engine < SSO_ENGINE_AUTO || c->engine > SSO_ENGINE_RESIDENT) return bad(SSO_E_INVAL, "unknown engine");
@@ -148,7 +164,7 @@ int validate_msg(const sso_config *c, const char **why)
     if ((1ull << 32) - threshold(t2) <= (1ull << 24))
         return bad(SSO_E_INVAL, "fresh interval must hold more than 2^24 words (1 - last threshold > 2^-8)");
     if (c->engine == SSO_ENGINE_RESIDENT && !resident_fits(c->n, c->d, c->kind))
-        return bad(SSO_E_UNSUPPORTED, "swarm does not fit the resident engine (one workgroup, separable objective)");
+        return bad(SSO_E_UNSUPPORTED, "swarm does not fit the resident engine (one workgroup; separable objective or Table 3.2 function)");
     if (c->polish_every != 0 && c->kind != SSO_OBJ_DENSE)
         return bad(SSO_E_UNSUPPORTED, "the gradient polish needs the dense objective");
     if (!(c->polish_lr == c->polish_lr) || std::isinf(c->polish_lr)) return bad(SSO_E_INVAL, "polish_lr must be finite");

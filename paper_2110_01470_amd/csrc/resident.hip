@@ -16,6 +16,7 @@
 // identical decisions.  On exit the state is written back with every pBest
 // in row 0 and every position in row 1.
 #include "sso_device.hpp"
+#include "sso_host.hpp"
 
 namespace sso {
 
@@ -30,11 +31,253 @@ static uint32_t resident_lanes(uint32_t d)
     return L;
 }
 
+// Table 3.2's functions: the STREAM engine's lanes per particle (its FP32
+// rule), one chunk per lane, up to kPaperMaxSlots particles per thread (with
+// more, the compiler no longer unrolls the loop over a thread's particles
+// and their registers go to scratch memory; one workgroup would not beat a
+// launch per generation there anyway).
+constexpr uint32_t kPaperMaxSlots = 4;
+
+namespace host {
+uint32_t resident_paper_slots(uint32_t n, uint32_t d)
+{
+    const uint32_t L = stream_lanes(d, STORE_F32);
+    const uint32_t chunks = (d + 3) / 4;
+    if (chunks > L || n == 0) return 0;
+    const uint32_t groups = kResidentMaxThreads / L;
+    const uint32_t slots = (n + groups - 1) / groups;
+    return slots <= kPaperMaxSlots ? slots : 0;
+}
+}  // namespace host
+
 bool resident_fits(uint32_t n, uint32_t d, int kind)
 {
+    if (is_paper_kind(kind)) return host::resident_paper_slots(n, d) != 0;
     if (kind != OBJ_SPHERE && kind != OBJ_RIPPLE) return false;
     const uint32_t L = resident_lanes(d);
     return L <= 64 && (uint64_t)n * L <= (uint64_t)kResidentMaxThreads;
+}
+
+// x op x' where x' is x of the lane that the row-local DPP control CTRL names.
+template <int CTRL>
+__device__ __forceinline__ float dpp_partner(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// The L-lane butterfly of paper_finish (partners at lane distance xor m,
+// m = L/2 down to 1; own value first) with the short distances as DPP moves
+// instead of LDS permutes.  m = 8 is row_ror:8 (lane l + 8 mod 16 is l ^ 8);
+// m = 4 is row_ror:4, whose source l + 4 mod 16 is l ^ 4 or (l ^ 4) ^ 8, and
+// after the m = 8 step lanes l and l ^ 8 hold the same value; m = 2 and 1
+// are quad permutes.  Every lane adds exactly the value the permute would
+// have brought, so the sums are bit for bit those of paper_finish.
+template <class Op>
+__device__ __forceinline__ float lane_fold(float x, uint32_t L, Op op)
+{
+    if (L > 32u) x = op(x, __shfl_xor(x, 32, 64));
+    if (L > 16u) x = op(x, __shfl_xor(x, 16, 64));
+    if (L > 8u) x = op(x, dpp_partner<0x128>(x));  // row_ror:8
+    if (L > 4u) x = L > 8u ? op(x, dpp_partner<0x124>(x))  // row_ror:4
+                           : op(x, __shfl_xor(x, 4, 64));
+    if (L > 2u) x = op(x, dpp_partner<0x4E>(x));    // quad_perm(2, 3, 0, 1)
+    if (L > 1u) x = op(x, dpp_partner<0xB1>(x));    // quad_perm(1, 0, 3, 2)
+    return x;
+}
+
+__device__ __forceinline__ float paper_fitness(PaperAcc q, uint32_t L, uint32_t d, int kind)
+{
+#pragma clang fp contract(off)
+    q.a = lane_fold(q.a, L, [](float u, float v) { return u + v; });
+    if (kind == OBJ_F1 + 5) q.b = lane_fold(q.b, L, [](float u, float v) { return u + v; });
+    if (kind == OBJ_F1 + 6) q.p = lane_fold(q.p, L, [](float u, float v) { return u * v; });
+    return paper_finish(q, 1u, d, kind);  // sums complete: only the function's last step
+}
+
+// Table 3.2's functions in one workgroup.  Lane ln of lane group g (L lanes,
+// the STREAM engine's count for this d, so chunk ln of every particle the
+// group holds) keeps chunk ln of particles g, g + G, ..., g + (P-1) G
+// (G groups) in registers, and evaluates each particle exactly as the STREAM
+// kernel does with the same L: paper_chunk on chunk ln, then paper_finish
+// over the L lanes.  So the two engines sum every fitness in the same order
+// and take the same decisions.
+//
+// One barrier per generation: before it, every wave posts its own best key
+// and its best particle's pBest row in LDS and adds its improved count to
+// the generation's counter; after it, every wave takes the minimum of the
+// posted keys and reads the winning wave's row as gBest.  The posts and
+// counters alternate between two buffers by generation, so a generation's
+// posts never overwrite the ones the previous generation is still reading
+// (every read of buffer b happens before the reader's next barrier, every
+// later write of b after it).  The lane sums are those of paper_finish with
+// the short distances as DPP moves (lane_fold).
+template <bool EQ21, int P>
+__global__ __launch_bounds__(kResidentMaxThreads) void k_resident_paper(SwarmDev S, uint32_t t_first,
+                                                                       uint32_t generations)
+{
+    __shared__ f4 s_row[2][kResidentMaxWaves][64];
+    __shared__ unsigned long long s_key[2][kResidentMaxWaves];
+    __shared__ uint32_t s_cnt[2];  // improved pBests of the generation (LDS atomics)
+
+    const uint32_t L = S.lanes;
+    const uint32_t lsh = (uint32_t)__builtin_ctz(L);
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t nwaves = blockDim.x >> 6;
+    const uint32_t ln = threadIdx.x & (L - 1u);
+    const uint32_t g = threadIdx.x >> lsh;
+    const uint32_t G = blockDim.x >> lsh;
+    const bool has_chunk = ln < S.chunks;
+
+    f4 xv[P], pv[P];
+    float fp[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        xv[p] = pv[p] = f4{0.f, 0.f, 0.f, 0.f};
+        fp[p] = 0.0f;
+        const uint32_t i = g + (uint32_t)p * G;
+        if (i < S.n) {
+            const uint32_t st = S.st[i];
+            const uint32_t prow = st & ST_ROW;
+            fp[p] = S.fp[i];
+            if (has_chunk) {
+                const size_t off = (size_t)i * S.stride;
+                const float *prow_ptr = S.rows + prow * S.buf + off;
+                const float *xrow_ptr = (st & ST_ALIAS) ? prow_ptr : S.rows + (1u - prow) * S.buf + off;
+                pv[p] = reinterpret_cast<const f4 *>(prow_ptr)[ln];
+                xv[p] = reinterpret_cast<const f4 *>(xrow_ptr)[ln];
+            }
+        }
+    }
+    // gBest of generation t_first - 1 from its sub-slot group (every wave
+    // reduces the 64 sub-slots itself); wave 0 records that generation in the
+    // trace ring.
+    // The latest generation's key (wave-uniform) and improved count (thread
+    // 0) stay in registers for the hand-off at the end.
+    f4 gv = f4{0.f, 0.f, 0.f, 0.f};
+    unsigned long long last_key;
+    uint32_t last_cnt = 0;
+    {
+        const uint32_t gr = (t_first - 1u) % kGroups;
+        const unsigned long long k0 = wave_min_u64(*sub_key(S, gr, lane));
+        last_key = k0;
+        if (threadIdx.x < 64u) {
+            uint32_t cc = *sub_cnt(S, gr, lane);
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) cc += __shfl_xor(cc, m, 64);
+            last_cnt = cc;
+            if (lane == 0) {
+                S.keys[(t_first - 1u) % S.trace_cap] = k0;
+                S.cnt[(t_first - 1u) % S.trace_cap] = cc;
+                s_cnt[0] = s_cnt[1] = 0u;
+            }
+        }
+        const uint32_t glow = (uint32_t)k0;
+        const uint32_t gidx = min(glow >> 1, S.n - 1u);
+        if (has_chunk)
+            gv = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf +
+                                             (size_t)gidx * S.stride)[ln];
+    }
+    __syncthreads();  // counters cleared
+
+    uint32_t slot = t_first % S.trace_cap;  // trace ring slot of generation t (thread 0)
+    for (uint32_t gen = 0; gen < generations; ++gen) {
+        const uint32_t t = t_first + gen;
+        const uint32_t b = gen & 1u;
+        unsigned long long key = ~0ull, kp[P];
+        uint32_t imp = 0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const uint32_t i = g + (uint32_t)p * G;
+            kp[p] = ~0ull;
+            bool improved = false;
+            if (i < S.n) {
+                PaperAcc q;
+                if (has_chunk) {
+                    const uint4 k = words4(S, ln, i, t);
+                    xv[p] = select4<EQ21>(S, k, gv, pv[p], xv[p]);
+                    paper_chunk(q, xv[p], ln, S.d, L, ln, S.kind);
+                }
+                const float f = paper_fitness(q, L, S.d, S.kind);
+                improved = improves(f, fp[p]);
+                if (improved) {
+                    pv[p] = xv[p];
+                    fp[p] = f;
+                }
+                kp[p] = gbest_key(fp[p], i, 0u);
+                key = min_u64(key, kp[p]);
+            }
+            imp += (uint32_t)__popcll(__ballot(improved && ln == 0u));
+        }
+        key = wave_min_u64(key);
+        // The wave's best particle posts its pBest row (its key is unique).
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            if (has_chunk && kp[p] == key) s_row[b][wave][ln] = pv[p];
+        if (lane == 0) {
+            s_key[b][wave] = key;
+            if (imp) atomicAdd(&s_cnt[b], imp);
+        }
+        __syncthreads();
+        // At most 16 posted keys: lanes 0..15, one DPP row.
+        static_assert(kResidentMaxWaves <= 16, "posted keys must fit one DPP row");
+        const unsigned long long posted = lane < nwaves ? s_key[b][lane] : ~0ull;
+        unsigned long long rmin = dpp_min_u64<0xB1>(posted);  // quad_perm(1, 0, 3, 2)
+        rmin = dpp_min_u64<0x4E>(rmin);                       // quad_perm(2, 3, 0, 1)
+        rmin = dpp_min_u64<0x141>(rmin);                      // row_half_mirror
+        rmin = dpp_min_u64<0x140>(rmin);                      // row_mirror
+        const unsigned long long best = readlane_u64(rmin, 0);
+        const uint32_t bw = (uint32_t)__builtin_ctzll(__ballot(posted == best));
+        if (has_chunk) gv = s_row[b][bw][ln];
+        last_key = best;
+        if (threadIdx.x == 0) {
+            // Cleared for generation gen + 2, whose adds come after this
+            // thread's next barrier.
+            last_cnt = s_cnt[b];
+            s_cnt[b] = 0u;
+            S.keys[slot] = best;
+            S.cnt[slot] = last_cnt;
+            slot = slot + 1u == S.trace_cap ? 0u : slot + 1u;
+        }
+    }
+
+    // Write back: pBest in row 0, position in row 1, no aliasing.
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const uint32_t i = g + (uint32_t)p * G;
+        if (i < S.n) {
+            const size_t off = (size_t)i * S.stride;
+            if (has_chunk) {
+                reinterpret_cast<f4 *>(S.rows + off)[ln] = pv[p];
+                reinterpret_cast<f4 *>(S.rows + S.buf + off)[ln] = xv[p];
+            }
+            if (ln == 0) {
+                S.st[i] = 0u;
+                S.fp[i] = fp[p];
+            }
+        }
+    }
+    // The last generation's result in sub-slot 0 of its group; the other
+    // groups cleared.
+    if (threadIdx.x < 64u) {
+        const uint32_t tl = t_first + generations - 1u;
+        for (uint32_t gr = 0; gr < kGroups; ++gr) {
+            const bool mine = gr == tl % kGroups && lane == 0;
+            *sub_key(S, gr, lane) = mine ? last_key : ~0ull;
+            *sub_cnt(S, gr, lane) = mine ? last_cnt : 0u;
+        }
+    }
+}
+
+template <bool EQ21>
+static void launch_paper_slots(const SwarmDev &S, uint32_t slots, uint32_t t_first, uint32_t gens,
+                               dim3 block, hipStream_t st)
+{
+    switch (slots) {
+    case 1: hipLaunchKernelGGL((k_resident_paper<EQ21, 1>), dim3(1), block, 0, st, S, t_first, gens); break;
+    case 2: hipLaunchKernelGGL((k_resident_paper<EQ21, 2>), dim3(1), block, 0, st, S, t_first, gens); break;
+    case 3: hipLaunchKernelGGL((k_resident_paper<EQ21, 3>), dim3(1), block, 0, st, S, t_first, gens); break;
+    default: hipLaunchKernelGGL((k_resident_paper<EQ21, 4>), dim3(1), block, 0, st, S, t_first, gens); break;
+    }
 }
 
 template <int KIND, int L, bool EQ21>
@@ -192,6 +435,26 @@ static void launch_k(const SwarmDev &S, uint32_t t_first, uint32_t gens, dim3 bl
 int launch_resident(const SwarmDev &S, uint32_t t_first, uint32_t generations, void *stream)
 {
     if (t_first == 0 || !resident_fits(S.n, S.d, S.kind)) return (int)hipErrorInvalidValue;
+    // No launch for no generations: the kernels' hand-off at the end assumes
+    // at least one generation's barrier lies between it and the first reads.
+    if (generations == 0) return (int)hipSuccess;
+    if (is_paper_kind(S.kind)) {
+        // The lanes must be the STREAM engine's FP32 count (the context sets
+        // them so); the gBest row is staged in 64 chunks of LDS at most.
+        if (S.lanes != host::stream_lanes(S.d, STORE_F32) || S.storage != STORE_F32 || S.chunks > 64u)
+            return (int)hipErrorInvalidValue;
+        // One particle per group when they all fit; otherwise the full
+        // workgroup, so that particle i sits in group i mod G of slot i / G:
+        // the slots fill in order and the partly filled last one spreads its
+        // waves over the SIMDs (waves w, w + 4, ... share one), which keeps
+        // the busiest SIMD's share of particle slots near the mean.
+        const uint32_t slots = host::resident_paper_slots(S.n, S.d);
+        const dim3 block(slots == 1u ? (S.n * S.lanes + 63u) / 64u * 64u : (uint32_t)kResidentMaxThreads);
+        hipStream_t st = (hipStream_t)stream;
+        if (S.order != 0) launch_paper_slots<true>(S, slots, t_first, generations, block, st);
+        else launch_paper_slots<false>(S, slots, t_first, generations, block, st);
+        return (int)hipGetLastError();
+    }
     const uint32_t threads = S.n * resident_lanes(S.d);
     const dim3 block((threads + 63u) / 64u * 64u);
     hipStream_t st = (hipStream_t)stream;

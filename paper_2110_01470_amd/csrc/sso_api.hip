@@ -87,19 +87,6 @@ Layout make_layout(const sso_config &c)
     return L;
 }
 
-// Lanes per particle for the STREAM engine: the chunk count rounded up to a
-// power of two, at least 8, at most 32 with 24-bit rows and 64 with FP32 rows
-// (measured on the ripple workload with D=1000: U24 131.9 us at 32 lanes vs
-// 135.1 at 64; F32 160.2 us at 64 vs 172.1 at 32).
-uint32_t stream_lanes(uint32_t d, int storage)
-{
-    const uint32_t chunks = (d + 3) / 4;
-    const uint32_t cap = storage == STORE_U24 ? 32u : 64u;
-    uint32_t L = 8;
-    while (L < chunks && L < cap) L <<= 1;
-    return L;
-}
-
 // Largest singular value of the DENSE matrix: power iteration on A^T A in
 // FP64 from the all-ones vector; the Rayleigh quotient ||A v||^2 converges
 // monotonically from below.  Run once, when a default step size is needed.
@@ -613,5 +600,14 @@ const char *sso_strerror(int code)
 }
 
 const char *sso_last_error(const sso_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+int sso_get_mapping(const sso_ctx *ctx, int *engine_out, int *storage_out, uint32_t *lanes_out)
+{
+    if (!ctx) return SSO_E_INVAL;
+    if (engine_out) *engine_out = ctx->engine;
+    if (storage_out) *storage_out = ctx->storage == STORE_U24 ? SSO_STORAGE_U24 : SSO_STORAGE_F32;
+    if (lanes_out) *lanes_out = ctx->S.lanes;
+    return SSO_OK;
+}
 
 }  // extern "C"

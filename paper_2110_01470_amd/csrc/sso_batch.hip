@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <iterator>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -21,10 +22,12 @@ namespace {
 constexpr uint32_t kGraphBlock = 50;       // generations per replayed graph
 constexpr uint32_t kMaxSwarms = 1u << 20;
 constexpr uint32_t kBatchMaxD = 1024;      // LDS staging of s, w and gBest
-constexpr uint32_t kWavesPerBlock = kStreamWaves;  // the batched kernel's workgroup
+constexpr uint32_t kMinWaves = 4;          // smallest workgroup the batched kernel is built for
 constexpr uint32_t kSubPerSlot = 8;        // workgroups per gBest sub-slot, at most
-const uint32_t kCandidates[] = {1, 2, 4, 8, 16};
+const uint32_t kCandidates[] = {1, 2, 4, 8, 16};   // mapping rules (chunks per lane)
+const uint32_t kWaveCandidates[] = {4, 8};          // waves per workgroup
 constexpr uint32_t kDefaultCpl = 8;
+constexpr uint32_t kDefaultWaves = kStreamWaves;
 
 thread_local std::string g_err;
 
@@ -39,6 +42,7 @@ struct sso_batch {
     SwarmDev *table_dev = nullptr;
     size_t max_tiles = 0;
     uint32_t cpl = kDefaultCpl;
+    uint32_t waves = kDefaultWaves;
     hipStream_t stream = nullptr;
     uint64_t t = 0;
     hipGraphExec_t exec = nullptr;
@@ -108,7 +112,7 @@ int validate_batch(const sso_config *cfgs, uint32_t count, std::string *why)
         if (c.order != cfgs[0].order) return bad(SSO_E_INVAL, "all swarms of a batch need the same order");
         if (batch_storage(c) != batch_storage(cfgs[0]))
             return bad(SSO_E_INVAL, "all swarms of a batch need the same storage");
-        tiles += (c.n + kWavesPerBlock - 1) / kWavesPerBlock;
+        tiles += (c.n + kMinWaves - 1) / kMinWaves;
     }
     if (tiles >= (1ull << 31)) {
         *why = "the batch needs more than 2^31 workgroups per launch";
@@ -124,8 +128,8 @@ BatchLayout make_batch_layout(const sso_config *cfgs, uint32_t count)
     L.max_tiles = 0;
     for (uint32_t k = 0; k < count; ++k) {
         // The most workgroups a swarm can take: 64 lanes per particle,
-        // 4 particles per workgroup.
-        L.max_tiles += (cfgs[k].n + kWavesPerBlock - 1) / kWavesPerBlock;
+        // 4 waves and so 4 particles per workgroup.
+        L.max_tiles += (cfgs[k].n + kMinWaves - 1) / kMinWaves;
     }
     size_t off = 0;
     L.head = off;    off += 256;
@@ -158,10 +162,11 @@ uint32_t rule_lanes(uint32_t chunks, uint32_t cpl, int storage)
     return L;
 }
 
-// Sets every swarm's lanes and sub-slot count for rule cpl and builds the
-// tile table: swarms in decreasing order of per-lane chunk count (the longest
-// workgroups are dispatched first), the blocks of a swarm consecutive.
-std::vector<uint32_t> plan(sso_batch *b, uint32_t cpl)
+// Sets every swarm's lanes and sub-slot count for rule cpl and workgroups
+// of `waves` waves, and builds the tile table: swarms in decreasing order of
+// per-lane chunk count (the longest workgroups are dispatched first), the
+// blocks of a swarm consecutive.
+std::vector<uint32_t> plan(sso_batch *b, uint32_t cpl, uint32_t waves)
 {
     const uint32_t count = (uint32_t)b->S.size();
     std::vector<uint32_t> tiles_of(count);
@@ -169,7 +174,7 @@ std::vector<uint32_t> plan(sso_batch *b, uint32_t cpl)
     for (uint32_t k = 0; k < count; ++k) {
         SwarmDev &S = b->S[k];
         const uint32_t L = b->fixed[k] ? b->fixed[k] : rule_lanes(S.chunks, cpl, S.storage);
-        const uint32_t per_block = kWavesPerBlock * (64 / L);
+        const uint32_t per_block = waves * (64 / L);
         S.lanes = L;
         tiles_of[k] = (S.n + per_block - 1) / per_block;
         uint32_t nsub = 1;
@@ -187,6 +192,7 @@ std::vector<uint32_t> plan(sso_batch *b, uint32_t cpl)
             tiles.push_back(blk);
         }
     b->cpl = cpl;
+    b->waves = waves;
     return tiles;
 }
 
@@ -202,15 +208,17 @@ void drop_graph(sso_batch *b)
     b->exec = nullptr;
 }
 
-// Uploads the mapping of rule cpl (swarm table and tile table); synchronous.
-int apply_plan(sso_batch *b, uint32_t cpl)
+// Uploads the mapping of rule cpl and workgroup size `waves` (swarm table
+// and tile table); synchronous.
+int apply_plan(sso_batch *b, uint32_t cpl, uint32_t waves)
 {
-    const std::vector<uint32_t> tiles = plan(b, cpl);
+    const std::vector<uint32_t> tiles = plan(b, cpl, waves);
     drop_graph(b);
     BHIP(hipStreamSynchronize(b->stream));
     BHIP(hipMemcpy(b->table_dev, b->S.data(), sizeof(SwarmDev) * b->S.size(), hipMemcpyHostToDevice));
     BHIP(hipMemcpy(b->tiles_dev, tiles.data(), sizeof(uint32_t) * tiles.size(), hipMemcpyHostToDevice));
     b->B.ntiles = (uint32_t)(tiles.size() / 2);
+    b->B.waves = waves;
     return SSO_OK;
 }
 
@@ -363,7 +371,7 @@ int sso_batch_init(const sso_config *cfgs, uint32_t count, void *ws, size_t ws_b
         rc = upload_separable(cfgs[k], b->S[k], b->stream, &b->err);
         if (rc != SSO_OK) return fail(rc);
     }
-    rc = apply_plan(b, kDefaultCpl);
+    rc = apply_plan(b, kDefaultCpl, kDefaultWaves);
     if (rc != SSO_OK) return fail(rc);
     rc = start(b);
     if (rc != SSO_OK) return fail(rc);
@@ -384,7 +392,8 @@ int sso_batch_run(sso_batch *b, uint32_t generations)
     return rc;
 }
 
-int sso_batch_tune(sso_batch *b, uint32_t generations, uint32_t *cpl_out, float *ms_out)
+int sso_batch_tune(sso_batch *b, uint32_t generations, uint32_t *cpl_out, uint32_t *waves_out,
+                   float *ms_out)
 {
     if (!b) return SSO_E_INVAL;
     if (b->t != 0) {
@@ -399,11 +408,14 @@ int sso_batch_tune(sso_batch *b, uint32_t generations, uint32_t *cpl_out, float 
         b->err = "hipEventCreate failed";
         return SSO_E_HIP;
     }
+    constexpr uint32_t nw = sizeof kWaveCandidates / sizeof kWaveCandidates[0];
+    constexpr uint32_t nc = sizeof kCandidates / sizeof kCandidates[0];
     int rc = SSO_OK;
     float best_ms = 0.0f;
-    uint32_t best = kDefaultCpl;
-    for (uint32_t q = 0; q < sizeof kCandidates / sizeof kCandidates[0] && rc == SSO_OK; ++q) {
-        rc = apply_plan(b, kCandidates[q]);
+    uint32_t best = kDefaultCpl, best_waves = kDefaultWaves;
+    for (uint32_t q = 0; q < nc * nw && rc == SSO_OK; ++q) {
+        const uint32_t cpl = kCandidates[q / nw], waves = kWaveCandidates[q % nw];
+        rc = apply_plan(b, cpl, waves);
         if (rc == SSO_OK) rc = start(b);
         if (rc == SSO_OK && hipEventRecord(e0, b->stream) != hipSuccess) rc = SSO_E_HIP;
         if (rc == SSO_OK) rc = enqueue(b, generations);
@@ -416,25 +428,49 @@ int sso_batch_tune(sso_batch *b, uint32_t generations, uint32_t *cpl_out, float 
         if (ms_out) ms_out[q] = ms;
         if (q == 0 || ms < best_ms) {
             best_ms = ms;
-            best = kCandidates[q];
+            best = cpl;
+            best_waves = waves;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (rc == SSO_OK) rc = apply_plan(b, best);
+    if (rc == SSO_OK) rc = apply_plan(b, best, best_waves);
     if (rc == SSO_OK) rc = start(b);
     if (rc == SSO_OK && hipStreamSynchronize(b->stream) != hipSuccess) {
         b->err = "synchronise after tuning failed";
         rc = SSO_E_HIP;
     }
     if (rc == SSO_OK && cpl_out) *cpl_out = best;
+    if (rc == SSO_OK && waves_out) *waves_out = best_waves;
     return rc;
 }
 
-int sso_batch_mapping(sso_batch *b, uint32_t *cpl_out, uint32_t *lanes_out, uint32_t *tiles_out)
+int sso_batch_set_mapping(sso_batch *b, uint32_t cpl, uint32_t waves)
+{
+    if (!b) return SSO_E_INVAL;
+    if (b->t != 0) {
+        b->err = "sso_batch_set_mapping needs a batch that has run no generations";
+        return SSO_E_STATE;
+    }
+    if (cpl == 0 || cpl > 64) {
+        b->err = "mapping rule (chunks per lane) must be in 1..64";
+        return SSO_E_INVAL;
+    }
+    if (std::find(std::begin(kWaveCandidates), std::end(kWaveCandidates), waves) == std::end(kWaveCandidates)) {
+        b->err = "waves per workgroup must be 4 or 8";
+        return SSO_E_INVAL;
+    }
+    int rc = apply_plan(b, cpl, waves);
+    if (rc == SSO_OK) rc = start(b);
+    return rc;
+}
+
+int sso_batch_mapping(sso_batch *b, uint32_t *cpl_out, uint32_t *waves_out, uint32_t *lanes_out,
+                      uint32_t *tiles_out)
 {
     if (!b) return SSO_E_INVAL;
     if (cpl_out) *cpl_out = b->cpl;
+    if (waves_out) *waves_out = b->waves;
     if (lanes_out)
         for (size_t k = 0; k < b->S.size(); ++k) lanes_out[k] = b->S[k].lanes;
     if (tiles_out) *tiles_out = b->B.ntiles;

@@ -248,8 +248,13 @@ struct PaperAcc {
     float a = 0.0f, b = 0.0f, p = 1.0f, carry = 0.0f;
 };
 
+// The functions below keep every product and sum a separate rounding (no
+// fused multiply-add contraction), so the value does not depend on how the
+// compiler schedules them in a given kernel: the STREAM and RESIDENT kernels
+// evaluate them identically.
 __device__ __forceinline__ float rosen_pair(float xi, float xn)
 {
+#pragma clang fp contract(off)
     const float q = xn - xi * xi, r = 1.0f - xi;
     return 100.0f * (q * q) + r * r;
 }
@@ -257,6 +262,7 @@ __device__ __forceinline__ float rosen_pair(float xi, float xn)
 __device__ __forceinline__ void paper_chunk(PaperAcc &q, f4 x, uint32_t c, uint32_t d, uint32_t L,
                                             uint32_t ln, int kind)
 {
+#pragma clang fp contract(off)
     const uint32_t j0 = 4u * c;
     const float v[4] = {x.x, x.y, x.z, x.w};
     switch (kind) {
@@ -301,8 +307,11 @@ __device__ __forceinline__ void paper_chunk(PaperAcc &q, f4 x, uint32_t c, uint3
 #pragma unroll
         for (uint32_t e = 0; e < 3; ++e)
             if (j0 + e + 1 < d) q.a += rosen_pair(v[e], v[e + 1]);
-        // The pair that straddles chunks c-1 and c belongs to chunk c.
-        const float below = __shfl_up(v[3], 1, L);
+        // The pair that straddles chunks c-1 and c belongs to chunk c.  The
+        // lane below (a DPP shift of the whole wave by one lane) is active
+        // whenever this lane is; lane 0 of a particle ignores what it gets.
+        const float below = __int_as_float(
+            __builtin_amdgcn_update_dpp(0, __float_as_int(v[3]), 0x138, 0xF, 0xF, false));  // wave_shr:1
         const float prev = ln ? below : q.carry;
         if (c > 0 && j0 < d) q.a += rosen_pair(prev, v[0]);
         q.carry = __shfl(v[3], L - 1, L);
@@ -349,12 +358,16 @@ __device__ __forceinline__ void paper_chunk(PaperAcc &q, f4 x, uint32_t c, uint3
 // L lanes, then the function's outer terms).
 __device__ __forceinline__ float paper_finish(PaperAcc q, uint32_t L, uint32_t d, int kind)
 {
+#pragma clang fp contract(off)
+    // Only Ackley uses the second sum and only Griewank the product; the
+    // others skip their (unused) reductions.
+    const bool need_b = kind == OBJ_F1 + 5, need_p = kind == OBJ_F1 + 6;
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1)
         if ((uint32_t)m < L) {
             q.a += __shfl_xor(q.a, m, 64);
-            q.b += __shfl_xor(q.b, m, 64);
-            q.p *= __shfl_xor(q.p, m, 64);
+            if (need_b) q.b += __shfl_xor(q.b, m, 64);
+            if (need_p) q.p *= __shfl_xor(q.p, m, 64);
         }
     const float P = (float)d;
     switch (kind) {

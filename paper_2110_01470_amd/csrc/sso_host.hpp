@@ -17,6 +17,18 @@ namespace host {
 constexpr uint32_t kDefaultTraceCap = 4096;
 
 size_t align256(size_t x);
+// Lanes per particle for the STREAM engine: the chunk count rounded up to a
+// power of two, at least 8, at most 32 with 24-bit rows and 64 with FP32 rows
+// (measured on the ripple workload with D=1000: U24 131.9 us at 32 lanes vs
+// 135.1 at 64; F32 160.2 us at 64 vs 172.1 at 32).  The RESIDENT engine's
+// kernel for Table 3.2's functions uses the same count.
+uint32_t stream_lanes(uint32_t d, int storage);
+// Table 3.2's functions on the RESIDENT engine (resident.hip): particles per
+// thread for a swarm of n particles of d variables (0 if it does not fit).
+uint32_t resident_paper_slots(uint32_t n, uint32_t d);
+// The most lanes (n times lanes per particle) for which the engine is chosen
+// automatically: 13 waves' worth of particles per SIMD.
+constexpr uint32_t kResidentPaperAutoLanes = 13u * 4u * 64u;
 uint32_t round_up(uint32_t x, uint32_t m);
 // ceil(c 2^32) for c in [0, 1] (exact: the product by 2^32 is exact).
 uint64_t threshold(double c);

@@ -35,8 +35,9 @@ enum { STORE_F32 = 0, STORE_U24 = 1 };
 enum : uint32_t { ST_ROW = 1u, ST_ALIAS = 2u };
 
 constexpr uint32_t kRowAlign = 32;      // floats per row alignment unit (128 B)
-// Waves per workgroup of the STREAM and batched kernels (measured on the
-// ripple workload: 4, 8 and 16 waves run within 0.5 % of each other).
+// Waves per workgroup of the STREAM kernel and the batched kernel's default
+// (measured on the ripple workload: 4, 8 and 16 waves run within 0.5 % of
+// each other); the batched kernel is also built for 8 (the autotuner's pick).
 #ifndef SSO_STREAM_WAVES
 #define SSO_STREAM_WAVES 4
 #endif
@@ -93,6 +94,7 @@ struct BatchDev {
     uint32_t *tbase;             // generations completed before the current block
     unsigned long long *results; // [count][2]: gBest key, improved count (collect)
     uint32_t count, ntiles;
+    uint32_t waves;              // waves per workgroup: 4 or 8
     uint32_t lds;                // dynamic LDS bytes per workgroup (largest swarm)
     int32_t kind, order, storage;
 };

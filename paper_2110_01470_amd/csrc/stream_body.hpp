@@ -55,8 +55,9 @@ inline size_t stage_bytes(const SwarmDev &S)
 // small enough to be latency-bound (Table 3.2 functions, N <= 350, D = 50);
 // the batched kernel, whose many short workgroups overlap one another, runs
 // faster without it (567 vs 569-572 us per generation of the 512 swarms).
+// WAVES: waves per workgroup (the batched kernel is built for 4 and 8).
 template <int KIND, int LT, bool EQ21, bool INIT, bool RAGGED, bool STAGE, class Store,
-          bool EARLY = true>
+          bool EARLY = true, int WAVES = kWaves>
 __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint32_t blk,
                                             uint32_t l)
 {
@@ -69,7 +70,7 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
     const uint32_t lane = tid & 63u, wave = tid >> 6;
     const uint32_t ln = lane & (L - 1u);
     // 64 / L particles per wave.
-    const uint32_t i = ((blk * kWaves + wave) << (6u - lsh)) + (lane >> lsh);
+    const uint32_t i = ((blk * WAVES + wave) << (6u - lsh)) + (lane >> lsh);
     const bool valid = i < S.n;
 
     // With EARLY the gBest key load goes out first (see generation_key_load).
@@ -204,7 +205,7 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
     }
     const unsigned long long key = valid ? gbest_key(fnew, i, row) : ~0ull;
 
-    generation_commit<kWaves>(S, t, blk, key, (improved && ln == 0) ? 1u : 0u);
+    generation_commit<WAVES>(S, t, blk, key, (improved && ln == 0) ? 1u : 0u);
 }
 
 }  // namespace sso

@@ -25,7 +25,7 @@ def test_header_declares_the_boundary():
                      "sso_batch_run", "sso_batch_tune", "sso_batch_get_results", "sso_eval",
                      "sso_polish"):
         assert required in names
-    assert len(names) == 27
+    assert len(names) == 29
 
 
 def test_library_exports_every_declared_symbol():
@@ -86,6 +86,8 @@ def test_split_contraction_adds_the_bf16_parts_of_a(d):
     dict(kind="dense", d=257, a=np.eye(257, dtype=np.float32)),
     dict(engine="resident", n=2000), dict(lo=-3e38, hi=3e38),
     dict(storage=7), dict(storage="u24", engine="resident"),
+    dict(kind="f4", s=None, d=50, n=300, engine="resident"),   # 5 particles per thread
+    dict(kind="f4", s=None, d=300, n=20, engine="resident"),   # 75 chunks, 64 lanes
     dict(polish_every=50, polish_steps=5), dict(kind="ripple", w=np.ones(30, np.float32), polish_every=1),
     dict(kind="dense", a=np.eye(30, dtype=np.float32), polish_lr=float("nan")),
     dict(storage="u24", kind="dense", a=np.eye(30, dtype=np.float32)),

@@ -103,19 +103,23 @@ def test_batch_graph_replays_back_to_back():
     assert batch.results()[3] == 303
 
 
-@pytest.mark.parametrize("rule", [None, 1, 16])
-def test_batch_swarm_equals_single_swarm_with_same_lanes(rule):
+@pytest.mark.parametrize("rule,waves", [(None, 4), (None, 8), (1, 4), (16, 8), ("tuned", None)])
+def test_batch_swarm_equals_single_swarm_with_same_lanes(rule, waves):
     """A swarm of a batch is the one-swarm library's run of the same config
-    when both use the same lanes per particle: bit-identical states."""
+    when both use the same lanes per particle, whatever the batch's
+    workgroup size: bit-identical states."""
     from paper_2110_01470_amd.binding import Batch, Swarm
 
     shapes = [(200, 300), (50, 37), (129, 64)]
     lanes = [8, 16, 32] if rule is None else [0, 0, 0]
     swarms = make_swarms(shapes=shapes, lanes=lanes, seed=500)
     batch = Batch(swarms)
-    if rule is not None:
-        batch.tune(1)  # any rule; then fix the lanes the batch uses
-    _, used, _ = batch.mapping()
+    if rule == "tuned":
+        batch.tune(1)  # any mapping; then fix the lanes the batch uses
+    else:
+        batch.set_mapping(8 if rule is None else rule, waves)
+        assert batch.mapping()[:2] == (8 if rule is None else rule, waves)
+    _, _, used, _ = batch.mapping()
     batch.run(60)
     checked = 0
     for k, sw in enumerate(swarms):
@@ -134,22 +138,25 @@ def test_batch_swarm_equals_single_swarm_with_same_lanes(rule):
 
 
 def test_batch_tune_picks_a_rule_and_restarts():
-    from paper_2110_01470_amd.binding import TUNE_CANDIDATES, Batch
+    from paper_2110_01470_amd.binding import TUNE_CANDIDATES, TUNE_WAVES, Batch
 
     swarms = make_swarms(seed=900)
     batch = Batch(swarms)
-    cpl, ms = batch.tune(3)
-    assert cpl in TUNE_CANDIDATES and set(ms) == set(TUNE_CANDIDATES)
+    assert batch.mapping()[:2] == (8, 4)  # the untuned default
+    cpl, waves, ms = batch.tune(3)
+    assert cpl in TUNE_CANDIDATES and waves in TUNE_WAVES
+    assert set(ms) == {(r, w) for r in TUNE_CANDIDATES for w in TUNE_WAVES}
     assert all(v > 0 for v in ms.values())
-    rule, lanes, tiles = batch.mapping()
-    assert rule == cpl
+    rule, wv, lanes, tiles = batch.mapping()
+    assert (rule, wv) == (cpl, waves)
     for k, sw in enumerate(swarms):
         chunks = (sw["d"] + 3) // 4
         L = 1
         while L * cpl < chunks and L < 32:
             L *= 2
         assert lanes[k] == L
-    assert tiles >= len(swarms)
+    # Workgroups per launch: each swarm's particles in blocks of waves * 64 / L.
+    assert tiles == sum(-(-sw["n"] // (waves * 64 // int(lanes[k]))) for k, sw in enumerate(swarms))
     # Back at generation 0 and in step with the oracle.
     pairs = pairs_for(batch, swarms)
     for pr in pairs:
@@ -175,6 +182,16 @@ def test_batch_set_state_and_errors():
     with pytest.raises(SSOError) as e:
         batch.view(5).state()
     assert e.value.code == E_INVAL
+    # A mapping is set only at generation 0, and only a known workgroup size.
+    with pytest.raises(SSOError) as e:
+        batch.set_mapping(8, 4)
+    assert e.value.code == E_STATE
+    fresh = Batch(swarms)
+    for rule, waves in ((8, 5), (0, 4), (65, 8), (4, 16)):
+        with pytest.raises(SSOError) as e:
+            fresh.set_mapping(rule, waves)
+        assert e.value.code == E_INVAL
+    assert fresh.mapping()[:2] == (8, 4)
 
 
 @pytest.mark.parametrize("storage", ["auto", "f32"])

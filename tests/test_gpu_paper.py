@@ -11,19 +11,19 @@ import pytest
 
 import oracle
 from paper_2110_01470_amd.inputs import PAPER_BOUNDS, PAPER_KINDS, PAPER_WORKLOADS
-from parity import Pair
+from parity import Pair, compare_after_run, oracle_run_with_trace
 
 pytestmark = pytest.mark.gpu
 
 
-def paper_pair(kind, n=100, d=50, order=oracle.ORDER_EQ21, seed=1001, **kw):
+def paper_pair(kind, n=100, d=50, order=oracle.ORDER_EQ21, seed=1001, engine="stream", **kw):
     lo, hi = PAPER_BOUNDS[kind]
     if order == oracle.ORDER_EQ21:
         cg, cp, cw = 0.8, 0.6, 0.3
     else:
         cg, cp, cw = 0.4, 0.7, 0.9
     return Pair(kind, n, d, lo=lo, hi=hi, cg=cg, cp=cp, cw=cw, seed=seed, order=order,
-                engine="stream", **kw)
+                engine=engine, **kw)
 
 
 @pytest.mark.parametrize("kind", PAPER_KINDS)
@@ -86,3 +86,84 @@ def test_full_run_reaches_paper_quality_band():
     assert t == 1000 and f == fp.min()
     assert 1.0 < f < 200.0
     assert abs(oracle.fitness(oracle.F1, g, None) - f) <= 1e-5 * f
+
+
+@pytest.mark.parametrize("kind", PAPER_KINDS)
+def test_resident_engine_generations(kind):
+    """Each function on the RESIDENT engine (one workgroup holds the swarm),
+    one launch per step, against the oracle at the paper's shape."""
+    pair = paper_pair(kind, engine="resident")
+    pair.compare()
+    pair.step(12)
+    assert pair.band_events <= 2
+
+
+@pytest.mark.parametrize("kind,n,d,order", [("f4", 200, 50, oracle.ORDER_EQ21),
+                                            ("f3", 100, 50, oracle.ORDER_EQ21),
+                                            ("f7", 129, 13, oracle.ORDER_GPS),
+                                            ("f8", 31, 130, oracle.ORDER_GPS),
+                                            ("f6", 5, 1, oracle.ORDER_EQ21),
+                                            ("f4", 256, 50, oracle.ORDER_EQ21),
+                                            ("f9", 131, 50, oracle.ORDER_GPS),
+                                            ("f6", 60, 100, oracle.ORDER_EQ21),
+                                            ("f7", 70, 50, oracle.ORDER_GPS)])
+def test_resident_equals_stream_bit_for_bit(kind, n, d, order):
+    """A whole run in one RESIDENT launch equals the STREAM engine's run at
+    the same lanes per particle bit for bit (positions, pBests, fitness,
+    trace), up to four particles per thread (N = 256 at D = 50), with 8, 16,
+    32 and 64 lanes per particle (D = 13, 50, 100, 130)."""
+    from paper_2110_01470_amd.binding import Swarm
+
+    lo, hi = PAPER_BOUNDS[kind]
+    cg, cp, cw = (0.8, 0.6, 0.3) if order == oracle.ORDER_EQ21 else (0.4, 0.7, 0.9)
+    runs = []
+    for engine in ("stream", "resident"):
+        sw = Swarm(n, d, kind, lo, hi, cg, cp, cw, 4242, None, order=order, engine=engine)
+        sw.run(150)
+        runs.append((sw.state(), sw.trace(0, 151), sw.best()))
+        sw.close()
+    (xa, pa, fa, ta), tra, ba = runs[0]
+    (xb, pb, fb, tb), trb, bb = runs[1]
+    assert ta == tb == 150
+    assert np.array_equal(xa, xb) and np.array_equal(pa, pb)
+    assert np.array_equal(fa.view(np.uint32), fb.view(np.uint32))
+    for u, v in zip(tra, trb):
+        assert np.array_equal(u, v)
+    assert ba[2] == bb[2] and np.array_equal(ba[0], bb[0])
+
+
+def test_resident_single_launch_against_oracle():
+    """Table 3.10's N = 200 Rosenbrock swarm, 300 generations in one RESIDENT
+    launch, against the oracle's run with the trace rule."""
+    wl = PAPER_WORKLOADS["paper_f4_n200_d50"]
+    pair = paper_pair("f4", n=wl.n, d=wl.d, seed=wl.seed, engine="resident")
+    trace = oracle_run_with_trace(pair.orc, 300)
+    pair.gpu.run(300)
+    assert compare_after_run(pair, 1, trace) in (0, 1)
+
+
+@pytest.mark.parametrize("kind,n,d,want", [("f4", 100, 50, ("resident", "f32", 16)),
+                                           ("f4", 208, 50, ("resident", "f32", 16)),
+                                           ("f4", 209, 50, ("stream", "u24", 16)),
+                                           ("f4", 350, 50, ("stream", "u24", 16)),
+                                           ("f1", 30, 130, ("resident", "f32", 64)),
+                                           ("sphere", 100, 30, ("resident", "f32", 8)),
+                                           ("ripple", 4096, 1000, ("stream", "u24", 32))])
+def test_auto_engine_choice(kind, n, d, want):
+    """AUTO takes the one-workgroup engine for Table 3.2's functions up to
+    N * L = 3328 lanes (13 waves per SIMD), STREAM beyond; the context
+    reports what it resolved to."""
+    from paper_2110_01470_amd.binding import Swarm
+
+    if kind in PAPER_BOUNDS:
+        lo, hi = PAPER_BOUNDS[kind]
+        s = w = None
+    else:
+        lo, hi = -100.0, 100.0
+        s = np.zeros(d, np.float32)
+        w = np.ones(d, np.float32) if kind == "ripple" else None
+    sw = Swarm(n, d, kind, lo, hi, 0.8, 0.6, 0.3, 7, s, w, order=oracle.ORDER_EQ21)
+    assert sw.mapping() == want
+    sw.run(2)
+    assert sw.best()[3] == 2
+    sw.close()
