@@ -49,8 +49,9 @@ extern "C" {
  * taken: F3 squares the running sums, F5 has the cosine, F6 has a = 20,
  * b = 0.2, c = 2 pi and + a + e, F8 sums Powell's four terms over the
  * floor(d/4) groups of four, F9 is meant for the box [-500, 500].  F1..F9
- * run on the STREAM engine with d <= 1024; they are not available to
- * batches or the RESIDENT engine. */
+ * run on the STREAM engine with d <= 1024, and on the RESIDENT engine when
+ * the swarm fits one workgroup (d <= 256, n at most 4 x 1024 / lanes per
+ * particle); they are not available to batches. */
 typedef enum {
     SSO_OBJ_SPHERE = 0, /* sum_j (x_j - s_j)^2                                  */
     SSO_OBJ_RIPPLE = 1, /* sum_j w_j (x_j - s_j)^2 + 0.5 sum_j sin^2(3(x_j - s_j)) */
@@ -76,7 +77,10 @@ typedef enum {
 typedef enum { SSO_ORDER_GPS = 0, SSO_ORDER_EQ21 = 1 } sso_order;
 
 /* Engines.  AUTO picks RESIDENT when the whole swarm fits one workgroup's
- * registers, else STREAM.  RESIDENT and STREAM with the same lanes per
+ * registers (for Table 3.2's functions: while it is also faster, see
+ * sso_get_mapping), else STREAM.  RESIDENT uses the STREAM engine's default
+ * lanes per particle and ignores the config's `lanes`.  RESIDENT and STREAM
+ * with the same lanes per
  * particle sum each fitness in the same order and give bit-identical runs;
  * another lanes setting sums in another order, so a pBest or gBest decision
  * between two fitness values a few FP32 ulps apart may go the other way. */
@@ -247,7 +251,8 @@ int sso_run_static(const sso_config *cfg, uint32_t generations, void *hip_stream
 /* What the context resolved its config to: *engine_out SSO_ENGINE_STREAM or
  * SSO_ENGINE_RESIDENT (AUTO takes RESIDENT for a separable swarm that fits
  * one workgroup, and for Table 3.2's functions while N times the lanes per
- * particle is at most 3328; STREAM otherwise), *storage_out SSO_STORAGE_F32
+ * particle is at most 256 times 16 (f1, f2, f4, f8), 13 (f3), 11 (f5),
+ * 9 (f6) or 10 (f7, f9); STREAM otherwise), *storage_out SSO_STORAGE_F32
  * or SSO_STORAGE_U24, *lanes_out the lanes per particle.  Any pointer may
  * be NULL.  Host only; SSO_E_INVAL for a NULL ctx. */
 int sso_get_mapping(const sso_ctx *ctx, int *engine_out, int *storage_out, uint32_t *lanes_out);

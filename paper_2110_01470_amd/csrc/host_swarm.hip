@@ -85,12 +85,14 @@ bool values_to_row(const SwarmDev &S, const float *in, uint32_t *row)
 bool resident_possible(const sso_config &c)
 {
     if (!resident_fits(c.n, c.d, c.kind)) return false;
-    // Table 3.2's functions: one workgroup's time grows with the particles
-    // each SIMD walks (about 0.29 us per wave of them, 1.08 us with one),
-    // a launch per generation costs about 4.4 us whatever N; measured on
-    // Rosenbrock, D = 50, the two meet near 13 waves per SIMD (N = 208).
-    return !is_paper_kind(c.kind) ||
-           (uint64_t)c.n * stream_lanes(c.d, STORE_F32) <= kResidentPaperAutoLanes;
+    // Table 3.2's functions: one workgroup's time grows with the waves of
+    // particles each SIMD walks (N L / 256), by 0.2-0.5 us per wave (more for
+    // the functions with transcendentals), while a launch per generation
+    // costs 4.3-5.1 us whatever N; the limits are where the two meet,
+    // measured at D = 50 and N = 100, 200, 256.
+    if (!is_paper_kind(c.kind)) return true;
+    const uint64_t waves = ((uint64_t)c.n * stream_lanes(c.d, STORE_F32) + 255u) / 256u;
+    return waves <= kResidentPaperAutoWaves[c.kind - SSO_OBJ_F1_SPHERE];
 }
 
 }  // namespace

@@ -26,9 +26,9 @@ uint32_t stream_lanes(uint32_t d, int storage);
 // Table 3.2's functions on the RESIDENT engine (resident.hip): particles per
 // thread for a swarm of n particles of d variables (0 if it does not fit).
 uint32_t resident_paper_slots(uint32_t n, uint32_t d);
-// The most lanes (n times lanes per particle) for which the engine is chosen
-// automatically: 13 waves' worth of particles per SIMD.
-constexpr uint32_t kResidentPaperAutoLanes = 13u * 4u * 64u;
+// Per function f1..f9, the most waves of particles per SIMD (n times lanes
+// per particle over 256) for which AUTO picks the one-workgroup engine.
+constexpr uint32_t kResidentPaperAutoWaves[9] = {16, 16, 13, 16, 11, 9, 10, 16, 10};
 uint32_t round_up(uint32_t x, uint32_t m);
 // ceil(c 2^32) for c in [0, 1] (exact: the product by 2^32 is exact).
 uint64_t threshold(double c);
