@@ -448,6 +448,11 @@ def main():
         achieved = byt / (ms_per_step / 1e3) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wl, window)}
+        if engine == "resident":
+            roofline["note"] = ("algorithmic rate only: the resident engine keeps the swarm in "
+                                "one workgroup's registers and touches HBM only at the start "
+                                "and end of the run; a generation is bound by that "
+                                "workgroup's dependent chain, not by HBM")
 
     cpu_gens = args.cpu_gens
     if cpu_gens is None:

@@ -7,9 +7,10 @@
 // up to a power of two), keeps X and P of that chunk in registers, and only
 // gBest and the argmin travel through LDS.  Per generation: Eq. (2.1) select
 // and objective terms in registers, an L-lane butterfly for the fitness, the
-// strict pBest test of Algorithm 3, a wave then workgroup minimum of the
-// (fitness, index) key for Algorithm 4, and the winning particle's lanes copy
-// its pBest into the LDS gBest row.  Two barriers per generation.
+// strict pBest test of Algorithm 3, a wave minimum of the (fitness, index)
+// key whose particle posts its pBest row to LDS, one barrier, and the
+// workgroup minimum over the posted keys for Algorithm 4, whose row is the
+// next gBest.
 //
 // Per lane the fitness is summed in the same order as the STREAM kernel with
 // the same L (one chunk per lane, then the butterfly), so both engines take
@@ -304,9 +305,13 @@ template <int KIND, int L, bool EQ21>
 __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, uint32_t t_first,
                                                                  uint32_t generations)
 {
-    __shared__ f4 s_g[kDenseMaxD / 4];
-    __shared__ unsigned long long s_key[kResidentMaxWaves];
-    __shared__ uint32_t s_cnt[kResidentMaxWaves];
+    // Per generation parity b: each wave's minimum key and its best
+    // particle's pBest row, and the generation's improved count (see
+    // k_resident_paper for why two buffers make one barrier enough).
+    __shared__ f4 s_row[2][kResidentMaxWaves][64];
+    __shared__ unsigned long long s_key[2][kResidentMaxWaves];
+    __shared__ uint32_t s_cnt[2];
+    static_assert(L <= 64, "a particle's chunks must fit one wave");
 
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t nwaves = blockDim.x >> 6;
@@ -316,7 +321,7 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, ui
     const bool owns = valid && c < S.chunks;     // lane holds real variables
 
     // Load the state of generation t_first - 1.
-    f4 xv = f4{0.f, 0.f, 0.f, 0.f}, pv = xv, sv = xv, wv = xv;
+    f4 xv = f4{0.f, 0.f, 0.f, 0.f}, pv = xv, sv = xv, wv = xv, gv = xv;
     float fp = 0.0f;
     if (valid) {
         const uint32_t st = S.st[i];
@@ -336,75 +341,87 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, ui
         sv = reinterpret_cast<const f4 *>(S.s)[c];
         if (KIND == OBJ_RIPPLE) wv = reinterpret_cast<const f4 *>(S.w)[c];
     }
+    // gBest of generation t_first - 1 from its sub-slot group (every wave
+    // reduces the 64 sub-slots itself); wave 0 records that generation in the
+    // trace ring.  The latest generation's key (wave-uniform) and improved
+    // count (thread 0) stay in registers for the hand-off at the end.
+    unsigned long long last_key;
+    uint32_t last_cnt = 0;
     {
-        // gBest of generation t_first - 1 from its sub-slot group; also
-        // records that generation in the trace ring.
-        __shared__ unsigned long long s_first;
+        const uint32_t gr = (t_first - 1u) % kGroups;
+        const unsigned long long k0 = wave_min_u64(*sub_key(S, gr, lane));
+        last_key = k0;
         if (threadIdx.x < 64u) {
-            const uint32_t g = (t_first - 1u) % kGroups;
-            unsigned long long k = *sub_key(S, g, lane);
-            uint32_t cc = *sub_cnt(S, g, lane);
-            k = wave_min_u64(k);
+            uint32_t cc = *sub_cnt(S, gr, lane);
 #pragma unroll
             for (int m = 32; m >= 1; m >>= 1) cc += __shfl_xor(cc, m, 64);
+            last_cnt = cc;
             if (lane == 0) {
-                s_first = k;
-                S.keys[(t_first - 1u) % S.trace_cap] = k;
+                S.keys[(t_first - 1u) % S.trace_cap] = k0;
                 S.cnt[(t_first - 1u) % S.trace_cap] = cc;
+                s_cnt[0] = s_cnt[1] = 0u;
             }
         }
-        __syncthreads();
-        const unsigned long long gk = s_first;
-        const uint32_t glow = (uint32_t)gk;
+        const uint32_t glow = (uint32_t)k0;
         const uint32_t gidx = min(glow >> 1, S.n - 1u);
-        const f4 *grow = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf +
-                                                      (size_t)gidx * S.stride);
-        for (uint32_t q = threadIdx.x; q < S.chunks; q += blockDim.x) s_g[q] = grow[q];
+        if (c < S.chunks)
+            gv = reinterpret_cast<const f4 *>(S.rows + (size_t)(glow & 1u) * S.buf +
+                                             (size_t)gidx * S.stride)[c];
     }
-    __syncthreads();
+    __syncthreads();  // counters cleared
 
+    uint32_t slot = t_first % S.trace_cap;  // trace ring slot of generation t (thread 0)
     for (uint32_t gen = 0; gen < generations; ++gen) {
-        const uint32_t t = t_first + gen;
+        const uint32_t b = gen & 1u;
         float acc = 0.0f;
         if (owns) {
-            const uint4 k = words4(S, c, i, t);
-            xv = select4<EQ21>(S, k, s_g[c], pv, xv);
+            const uint4 k = words4(S, c, i, t_first + gen);
+            xv = select4<EQ21>(S, k, gv, pv, xv);
             acc += terms4<KIND>(xv, sv, wv, 4u * c, S.d);
         }
-#pragma unroll
-        for (int m = L / 2; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+        acc = lane_fold(acc, L, [](float u, float v) { return u + v; });
         const bool improved = valid && improves(acc, fp);
         if (improved) {
             pv = xv;
             fp = acc;
         }
-        unsigned long long key = valid ? gbest_key(fp, i, 0u) : ~0ull;
+        const unsigned long long mine = valid ? gbest_key(fp, i, 0u) : ~0ull;
         // Keys are equal within a particle's lanes, so the masks from L up
         // suffice; a few permutes are cheaper here than the full DPP minimum.
+        unsigned long long key = mine;
 #pragma unroll
         for (int m = 32; m >= L; m >>= 1) {
             const uint32_t lo = __shfl_xor((uint32_t)key, m, 64);
             const uint32_t hi = __shfl_xor((uint32_t)(key >> 32), m, 64);
             key = min_u64(key, ((unsigned long long)hi << 32) | lo);
         }
+        // The wave's best particle posts its pBest row (its key is unique).
+        if (c < S.chunks && mine == key) s_row[b][wave][c] = pv;
         const uint32_t cnt = (uint32_t)__popcll(__ballot(improved && c == 0));
         if (lane == 0) {
-            s_key[wave] = key;
-            s_cnt[wave] = cnt;
+            s_key[b][wave] = key;
+            if (cnt) atomicAdd(&s_cnt[b], cnt);
         }
         __syncthreads();
-        unsigned long long best = s_key[0];
-        for (uint32_t w = 1; w < nwaves; ++w) best = min_u64(best, s_key[w]);
-        const uint32_t gidx = (uint32_t)best >> 1;
-        if (owns && i == gidx) s_g[c] = pv;
+        // At most 16 posted keys: lanes 0..15, one DPP row.
+        const unsigned long long posted = lane < nwaves ? s_key[b][lane] : ~0ull;
+        unsigned long long rmin = dpp_min_u64<0xB1>(posted);  // quad_perm(1, 0, 3, 2)
+        rmin = dpp_min_u64<0x4E>(rmin);                       // quad_perm(2, 3, 0, 1)
+        rmin = dpp_min_u64<0x141>(rmin);                      // row_half_mirror
+        rmin = dpp_min_u64<0x140>(rmin);                      // row_mirror
+        const unsigned long long best = readlane_u64(rmin, 0);
+        const uint32_t bw = (uint32_t)__builtin_ctzll(__ballot(posted == best));
+        if (c < S.chunks) gv = s_row[b][bw][c];
+        last_key = best;
         if (threadIdx.x == 0) {
-            uint32_t total = 0;
-            for (uint32_t w = 0; w < nwaves; ++w) total += s_cnt[w];
-            const uint32_t slot = t % S.trace_cap;
+            // Cleared for generation gen + 2, whose adds come after this
+            // thread's next barrier.
+            last_cnt = s_cnt[b];
+            s_cnt[b] = 0u;
             S.keys[slot] = best;
-            S.cnt[slot] = total;
+            S.cnt[slot] = last_cnt;
+            slot = slot + 1u == S.trace_cap ? 0u : slot + 1u;
         }
-        __syncthreads();
     }
 
     // Write back: pBest in row 0, position in row 1, no aliasing.
@@ -423,12 +440,10 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident(SwarmDev S, ui
     // the host) looks for it: sub-slot 0 of its group; clear the other groups.
     if (threadIdx.x < 64u) {
         const uint32_t tl = t_first + generations - 1u;
-        const unsigned long long best = S.keys[tl % S.trace_cap];
-        const uint32_t total = S.cnt[tl % S.trace_cap];
         for (uint32_t g = 0; g < kGroups; ++g) {
-            const bool mine = g == tl % kGroups && lane == 0;
-            *sub_key(S, g, lane) = mine ? best : ~0ull;
-            *sub_cnt(S, g, lane) = mine ? total : 0u;
+            const bool own = g == tl % kGroups && lane == 0;
+            *sub_key(S, g, lane) = own ? last_key : ~0ull;
+            *sub_cnt(S, g, lane) = own ? last_cnt : 0u;
         }
     }
 }
