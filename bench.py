@@ -358,8 +358,8 @@ def main():
     ap.add_argument("--tune-gens", type=int, default=5,
                     help="generations the batch mapping tuner times per candidate")
     ap.add_argument("--engine", default="auto", choices=["auto", "stream", "resident"])
-    ap.add_argument("--contraction", default="auto", choices=["auto", "f32", "bf16x3"],
-                    help="dense objective: FP32 or split-bf16 matrix cores")
+    ap.add_argument("--contraction", default="auto", choices=["auto", "f32", "bf16x3", "f16x2"],
+                    help="dense objective: FP32, split-bf16 or split-fp16 matrix cores")
     ap.add_argument("--cpu-gens", type=int, default=None,
                     help="oracle generations for cpu_baseline (0 = skip)")
     ap.add_argument("--ceilings", action="store_true",
@@ -407,15 +407,15 @@ def main():
     window = timed_window(wl, steps)
     log(f"workload {wl.name}: N={wl.n} D={wl.d} steps={steps} warmup={args.warmup}, "
         f"timed generations {window[0]}..{window[1]}")
-    ms, fg, gen, (engine, storage, lanes) = time_gpu(wl, steps, args.warmup, args.engine,
-                                                     args.contraction)
+    ms, fg, gen, (engine, storage, lanes, contraction) = time_gpu(wl, steps, args.warmup,
+                                                                   args.engine, args.contraction)
     sec = ms / 1e3
     updates = wl.n * wl.d * steps
     value = updates / sec
     ms_per_step = ms / steps
     log(f"gpu: {ms:.3f} ms for {steps} generations, fG={fg:.6g} at t={gen}")
 
-    split = wl.kind == "dense" and args.contraction != "f32"
+    split = wl.kind == "dense" and contraction != "f32"
     f32_line = None
     if split:
         # The FP32 contraction the workload names, timed over the same window
@@ -427,15 +427,17 @@ def main():
                     "traffic": measured_traffic(wl, window, wl.name + "/f32")}
         log(f"gpu, FP32 contraction: {ms32:.3f} ms for {steps} generations")
     if split:
-        # The split contraction runs six bf16 products per FP32 product on the
-        # bf16 matrix cores: priced at their work and their peak.  The
+        # A split contraction runs six bf16 (BF16X3) or three fp16 (F16X2)
+        # products per FP32 product on the 16-bit matrix cores (the same
+        # dense peak for both types): priced at their work and that peak.  The
         # FP32-equivalent rate against the FP32 matrix peak is given beside it.
-        flop = 6 * 2.0 * wl.n * wl.d * wl.d
+        products = 3 if contraction == "f16x2" else 6
+        flop = products * 2.0 * wl.n * wl.d * wl.d
         achieved = flop / (ms_per_step / 1e3) / 1e12
-        fp32_eq = achieved / 6 / FP32_MATRIX_PEAK_TFLOPS
+        fp32_eq = achieved / products / FP32_MATRIX_PEAK_TFLOPS
         roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_MATRIX_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": achieved / BF16_MATRIX_PEAK_TFLOPS,
-                    "traffic": measured_traffic(wl, window, wl.name + "/bf16x3"),
+                    "traffic": measured_traffic(wl, window, wl.name + "/" + contraction),
                     "fp32_equivalent_frac": fp32_eq}
     elif wl.kind == "dense":
         flop = 2.0 * wl.n * wl.d * wl.d
@@ -487,12 +489,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x3" if split else "f32",
+        "dtype": contraction if split else "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "objective": wl.kind, "n": wl.n, "d": wl.d,
                    "generations": max(steps, wl.generations),
                    "timed_generations": list(window), "engine": engine,
-                   **({"contraction": "f32" if args.contraction == "f32" else "bf16x3"}
+                   **({"contraction": contraction}
                       if wl.kind == "dense" else {"row_storage": storage,
                                                   "lanes_per_particle": lanes})},
         "roofline": roofline,
@@ -555,7 +557,7 @@ def bench_paper(pw, args):
     e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1)
-    engine, storage, lanes = sw.mapping()
+    engine, storage, lanes, _ = sw.mapping()
     ms_per_step = ms / steps
     updates = pw.n * pw.d * steps
     log(f"{pw.name}: whole run {wall * 1e3:.2f} ms (median of 5), generations {ms:.2f} ms, "
@@ -684,6 +686,7 @@ def bench_polish(wl, args):
         sw.close()
     # The polish kernel alone: (4 steps + 2) N D^2 FLOP per call.
     sw = Swarm(*args_, stream=stream, contraction=args.contraction)
+    contraction = sw.mapping()[3]
     sw.run(10)
     lr = sw.polish(POLISH_STEPS)
     reps = 20
@@ -725,12 +728,12 @@ def bench_polish(wl, args):
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.contraction == "f32" else "bf16x3",
+        "dtype": contraction,
         "data": "synthetic",
         "config": {"workload": wl.name + "+polish", "objective": wl.kind, "n": wl.n, "d": wl.d,
                    "generations": steps, "polish_every": POLISH_EVERY, "polish_steps": POLISH_STEPS,
                    "polish_lr": lr,
-                   "contraction": "f32" if args.contraction == "f32" else "bf16x3",
+                   "contraction": contraction,
                    "polish_contraction": "f32"},
         "gap": {"target": gap_target, "compared_at": gap,
                 "time_to_target_ms": reached,

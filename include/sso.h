@@ -104,9 +104,23 @@ typedef enum { SSO_STORAGE_AUTO = 0, SSO_STORAGE_F32 = 1, SSO_STORAGE_U24 = 2 } 
  * F32: on FP32 matrix cores (v_mfma_f32_16x16x4_f32).
  * BF16X3: every FP32 operand is split exactly into three bf16 parts and the
  * six part products above 2^-24 relative weight go through bf16 matrix
- * cores with FP32 accumulation (the three omitted are below 2^-23 |a d|);
- * the device holds a second copy of A, 6 dp^2 bytes.  AUTO = BF16X3. */
-typedef enum { SSO_CONTRACT_AUTO = 0, SSO_CONTRACT_F32 = 1, SSO_CONTRACT_BF16X3 = 2 } sso_contraction;
+ * cores with FP32 accumulation (the three omitted are below 2^-23 |a d|).
+ * F16X2: each row of A, and the differences x - s, are scaled by powers of
+ * two into fp16's range (from A, s and the box) and split into two fp16
+ * parts; the three products of weight 2^-11 or more go through fp16 matrix
+ * cores with FP32 accumulation (each exact in FP32; what is left out is
+ * below 2^-20 |a d|, or below 2^-49 of the row's or the box's largest
+ * magnitude for entries under 2^-27 of it).  Half the matrix-core work of
+ * BF16X3.  Needs finite A and s with magnitudes within 2^+-100 of one
+ * another (SSO_E_INVAL otherwise), and, in sso_set_state, positions inside
+ * [lo, hi].  Both split forms hold a second copy of A (6 dp^2 bytes).
+ * AUTO = F16X2 when the instance fits it, BF16X3 otherwise. */
+typedef enum {
+    SSO_CONTRACT_AUTO = 0,
+    SSO_CONTRACT_F32 = 1,
+    SSO_CONTRACT_BF16X3 = 2,
+    SSO_CONTRACT_F16X2 = 3
+} sso_contraction;
 
 typedef struct {
     uint32_t n;          /* Nsol, particles, >= 1, < 2^31                         */
@@ -253,9 +267,12 @@ int sso_run_static(const sso_config *cfg, uint32_t generations, void *hip_stream
  * one workgroup, and for Table 3.2's functions while N times the lanes per
  * particle is at most 256 times 16 (f1, f2, f4, f8), 13 (f3), 11 (f5),
  * 9 (f6) or 10 (f7, f9); STREAM otherwise), *storage_out SSO_STORAGE_F32
- * or SSO_STORAGE_U24, *lanes_out the lanes per particle.  Any pointer may
- * be NULL.  Host only; SSO_E_INVAL for a NULL ctx. */
-int sso_get_mapping(const sso_ctx *ctx, int *engine_out, int *storage_out, uint32_t *lanes_out);
+ * or SSO_STORAGE_U24, *lanes_out the lanes per particle, *contraction_out
+ * the dense kernel's SSO_CONTRACT_F32, _BF16X3 or _F16X2 (F32 for the other
+ * objectives).  Any pointer may be NULL.  Host only; SSO_E_INVAL for a NULL
+ * ctx. */
+int sso_get_mapping(const sso_ctx *ctx, int *engine_out, int *storage_out, uint32_t *lanes_out,
+                    int *contraction_out);
 
 /* Static text for an SSO_* code. */
 const char *sso_strerror(int code);

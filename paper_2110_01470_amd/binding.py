@@ -20,7 +20,7 @@ OBJ = {"sphere": 0, "ripple": 1, "dense": 2, "f1": 11, "f2": 12, "f3": 13, "f4":
 ORDER_GPS, ORDER_EQ21 = 0, 1
 ENGINE = {"auto": 0, "stream": 1, "resident": 2}
 STORAGE = {"auto": 0, "f32": 1, "u24": 2}
-CONTRACTION = {"auto": 0, "f32": 1, "bf16x3": 2}
+CONTRACTION = {"auto": 0, "f32": 1, "bf16x3": 2, "f16x2": 3}
 
 
 class SSOError(RuntimeError):
@@ -86,7 +86,7 @@ def load():
         "sso_run_static": (ctypes.c_int, [cfgp, u32, P, P, P, P]),
         "sso_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sso_last_error": (ctypes.c_char_p, [P]),
-        "sso_get_mapping": (ctypes.c_int, [P, P, P, P]),
+        "sso_get_mapping": (ctypes.c_int, [P, P, P, P, P]),
         "sso_batch_workspace_bytes": (ctypes.c_size_t, [cfgp, u32]),
         "sso_batch_init": (ctypes.c_int, [cfgp, u32, P, ctypes.c_size_t, P, ctypes.POINTER(P)]),
         "sso_batch_run": (ctypes.c_int, [P, u32]),
@@ -226,16 +226,19 @@ class Swarm:
         return self
 
     def mapping(self):
-        """(engine, row storage, lanes per particle) the config resolved to,
-        as names ("stream"/"resident", "f32"/"u24")."""
+        """(engine, row storage, lanes per particle, dense contraction) the
+        config resolved to, as names ("stream"/"resident", "f32"/"u24",
+        lanes, "f32"/"bf16x3"/"f16x2")."""
         eng = ctypes.c_int()
         sto = ctypes.c_int()
         lanes = ctypes.c_uint32()
+        con = ctypes.c_int()
         self._check(self._lib.sso_get_mapping(self._ctx, ctypes.byref(eng), ctypes.byref(sto),
-                                              ctypes.byref(lanes)))
+                                              ctypes.byref(lanes), ctypes.byref(con)))
         names = {v: k for k, v in ENGINE.items()}
         stores = {v: k for k, v in STORAGE.items()}
-        return names[eng.value], stores[sto.value], int(lanes.value)
+        cons = {v: k for k, v in CONTRACTION.items()}
+        return names[eng.value], stores[sto.value], int(lanes.value), cons[con.value]
 
     def best(self):
         """(g [d], fG, gidx, generations done)."""

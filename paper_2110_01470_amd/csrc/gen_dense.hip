@@ -28,8 +28,10 @@
 // step's copy and the next select's row loads are issued before the current
 // step's MFMAs, which read their A operands from LDS four row blocks at a
 // time.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "sso_device.hpp"
 
@@ -352,6 +354,104 @@ void dense_pack_split(const float *a, uint32_t d, uint16_t *out)
         }
 }
 
+// Two-part fp16 split (contraction F16X2).  Row k of A is scaled by 2^e_k
+// and the differences d = x - s by 2^e_d, powers of two that put the largest
+// |a_kj| in [2^13, 2^14) and every |d_j| below 2^13 (from the box and the
+// shift), well inside fp16's range; a scaled value v is split into
+// h = fp16(v) and m = fp16((v - h) 2^11), each rounded to nearest.  The
+// kernel takes the products h_a h_d, h_a m_d and m_a h_d (fp16 products are
+// exact in FP32) and forms y_k = (sum h h + 2^-11 sum (h m + m h)) 2^-(e_k +
+// e_d).  Layout: the parts as [step][row block][part][lane][8 halves]
+// (2 dp^2 halves), then dp row factors 2^-(e_k + e_d), then 2^e_d (floats).
+uint64_t dense_f16x2_halves(uint32_t d)
+{
+    const uint64_t dp = (d + kRowAlign - 1) / kRowAlign * kRowAlign;
+    return 2u * dense_matrix_floats(d) + 2u * (dp + 4u);
+}
+
+namespace {
+
+// e with 2^(e - 1) <= x < 2^e, for finite x > 0.
+int exponent_above(double x)
+{
+    int e = 0;
+    (void)std::frexp(x, &e);
+    return e;
+}
+
+uint16_t f16_bits(float v)
+{
+    const _Float16 h = (_Float16)v;  // round to nearest even, subnormals included
+    uint16_t u;
+    memcpy(&u, &h, 2);
+    return u;
+}
+
+float f16_value(uint16_t u)
+{
+    _Float16 h;
+    memcpy(&h, &u, 2);
+    return (float)h;
+}
+
+}  // namespace
+
+bool dense_pack_f16x2(const float *a, uint32_t d, const float *s, float lo, float hi, uint16_t *out)
+{
+    const uint32_t dp = (d + kRowAlign - 1) / kRowAlign * kRowAlign;
+    const uint32_t nb = dp / 16, steps = dp / 32;
+    double dmax = 0.0;
+    for (uint32_t j = 0; j < d; ++j) {
+        if (!std::isfinite(s[j])) return false;
+        dmax = std::max(dmax, std::max(std::fabs((double)lo - s[j]), std::fabs((double)hi - s[j])));
+    }
+    if (!std::isfinite(dmax)) return false;
+    const int ed = dmax > 0.0 ? 13 - exponent_above(dmax) : 0;
+    if (ed < -100 || ed > 100) return false;
+    // Row exponents (checked without allocating; kept only when packing).
+    auto row_exp = [&](uint32_t k, int *e) {
+        double amax = 0.0;
+        for (uint32_t j = 0; j < d; ++j) {
+            const float v = a[(size_t)k * d + j];
+            if (!std::isfinite(v)) return false;
+            amax = std::max(amax, (double)std::fabs(v));
+        }
+        *e = amax > 0.0 ? 14 - exponent_above(amax) : 0;
+        return *e >= -100 && *e <= 100 && *e + ed >= -120 && *e + ed <= 120;
+    };
+    for (uint32_t k = 0; k < d; ++k) {
+        int e = 0;
+        if (!row_exp(k, &e)) return false;
+    }
+    if (!out) return true;
+    std::vector<int> er(dp, 0);
+    for (uint32_t k = 0; k < d; ++k) (void)row_exp(k, &er[k]);
+    size_t o = 0;
+    for (uint32_t m = 0; m < steps; ++m)
+        for (uint32_t rb = 0; rb < nb; ++rb) {
+            uint16_t part[2][64][8];
+            for (uint32_t lane = 0; lane < 64; ++lane)
+                for (uint32_t e = 0; e < 8; ++e) {
+                    const uint32_t k = 16 * rb + lane % 16;
+                    const uint32_t j = 32 * m + 8 * (lane / 16) + e;
+                    const float v = (k < d && j < d) ? (float)std::ldexp((double)a[(size_t)k * d + j], er[k])
+                                                     : 0.0f;
+                    const uint16_t h = f16_bits(v);
+                    part[0][lane][e] = h;
+                    part[1][lane][e] = f16_bits((v - f16_value(h)) * 2048.0f);
+                }
+            for (uint32_t p = 0; p < 2; ++p)
+                for (uint32_t lane = 0; lane < 64; ++lane)
+                    for (uint32_t e = 0; e < 8; ++e) out[o++] = part[p][lane][e];
+        }
+    float tail[4] = {(float)std::ldexp(1.0, ed), 0.f, 0.f, 0.f};
+    std::vector<float> rf(dp);
+    for (uint32_t k = 0; k < dp; ++k) rf[k] = (float)std::ldexp(1.0, -(er[k] + ed));
+    memcpy(out + o, rf.data(), sizeof(float) * dp);
+    memcpy(out + o + 2u * dp, tail, sizeof tail);
+    return true;
+}
+
 // The generation kernel.  The 64 particles of a workgroup are spread over
 // eight waves, two per SIMD, so that one wave's matrix-core work runs while
 // the other selects or waits.
@@ -372,6 +472,8 @@ void dense_pack_split(const float *a, uint32_t d, uint16_t *out)
 // flight the compiler waits for every outstanding load before it uses any
 // loaded register, which would drain the prefetch of later steps each step.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
 // The three bf16 parts of four FP32 values.
 __device__ __forceinline__ void split3x4(f4 d, bf16x4 &h, bf16x4 &m, bf16x4 &l)
@@ -388,14 +490,28 @@ __device__ __forceinline__ void split3x4(f4 d, bf16x4 &h, bf16x4 &m, bf16x4 &l)
     }
 }
 
-template <int NB, bool EQ21, bool INIT, bool FULL_D>
+// The two fp16 parts of four scaled FP32 values (contraction F16X2).
+__device__ __forceinline__ void split2x4(f4 v, half4 &h, half4 &m)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const _Float16 v1 = (_Float16)v[j];
+        h[j] = v1;
+        m[j] = (_Float16)((v[j] - (float)v1) * 2048.0f);
+    }
+}
+
+// F16: the two-part fp16 split (three products, two accumulators) instead
+// of the three-part bf16 one (six products).
+template <int NB, bool EQ21, bool INIT, bool FULL_D, bool F16>
 __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
 {
+    constexpr uint32_t PARTS = F16 ? 2u : 3u;
     constexpr uint32_t STEPS = NB / 2;              // 32 variables per step
-    constexpr uint32_t STEP_U = NB * 3u * 64u;      // 16-byte units of A per step
+    constexpr uint32_t STEP_U = NB * PARTS * 64u;   // 16-byte units of A per step
     constexpr uint32_t PER = (STEP_U + 511u) / 512u;
     constexpr bool FULL = STEP_U % 512u == 0;
-    constexpr uint32_t B_U = 4u * 3u * 64u;         // 16-byte units of d parts per step
+    constexpr uint32_t B_U = 4u * PARTS * 64u;      // 16-byte units of d parts per step
     __shared__ f4 lda0[STEP_U];
     __shared__ f4 lda1[STEP_U];
     __shared__ f4 ldb0[B_U];
@@ -410,8 +526,11 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
     // n - 1 (same rows and words, the same values to the same addresses) and
     // its fitness is not used: the select has no branch.
     const uint32_t ie = ip < S.n ? ip : S.n - 1u;
-    const uint32_t bsl = ((pl >> 4) * 3u * 64u + (pl & 15u) + 16u * (q >> 1)) * 2u + (q & 1u);
+    const uint32_t bsl = ((pl >> 4) * PARTS * 64u + (pl & 15u) + 16u * (q >> 1)) * 2u + (q & 1u);
     const f4 *a_pack = reinterpret_cast<const f4 *>(S.a3);
+    // F16X2: row factors after the parts, then the scale of d.
+    const float *rfac = reinterpret_cast<const float *>(S.a3 + 2u * NB * 16u * NB * 16u);
+    const float dsc = F16 ? rfac[NB * 16u] : 1.0f;
 
     unsigned long long gkey = ~0ull;
     if constexpr (!INIT) gkey = generation_key_load(S, t);
@@ -524,12 +643,20 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
                 dv.w = (j0 + 3 < S.d) ? xn.w - sv[b].w : 0.f;
             }
         }
-        bf16x4 h, md, lo;
-        split3x4(dv, h, md, lo);
-        bf16x4 *dst = reinterpret_cast<bf16x4 *>(db);
-        dst[bsl] = h;
-        dst[bsl + 128u] = md;
-        dst[bsl + 256u] = lo;
+        if constexpr (F16) {
+            half4 h, md;
+            split2x4(dv * dsc, h, md);  // the scale is a power of two: exact
+            half4 *dst = reinterpret_cast<half4 *>(db);
+            dst[bsl] = h;
+            dst[bsl + 128u] = md;
+        } else {
+            bf16x4 h, md, lo;
+            split3x4(dv, h, md, lo);
+            bf16x4 *dst = reinterpret_cast<bf16x4 *>(db);
+            dst[bsl] = h;
+            dst[bsl + 128u] = md;
+            dst[bsl + 256u] = lo;
+        }
     };
 
     select_step(0, 0, ldb0);
@@ -540,6 +667,12 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
 #pragma unroll
         for (uint32_t pt = 0; pt < 4; ++pt) acc[r][pt] = zero4;
     const bool mine = NB >= 16 || 2u * wave < (uint32_t)NB;  // this wave owns row blocks
+    // F16X2: the cross products h m + m h, scaled by 2^-11 at the end.
+    f4 acc2[2][4];
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r)
+#pragma unroll
+        for (uint32_t pt = 0; pt < 4; ++pt) acc2[r][pt] = zero4;
 
     __syncthreads();  // A block 0 and step 0's d parts are in LDS
 
@@ -557,39 +690,63 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
         if (mine) {
             const f4 *la = cur ? lda1 : lda0;
             const f4 *lb = cur ? ldb1 : ldb0;
-            bf16x8 bh[4], bm[4], bl[4];
+            if constexpr (F16) {
+                half8 bh[4], bm[4];
 #pragma unroll
-            for (uint32_t pt = 0; pt < 4; ++pt) {
-                bh[pt] = __builtin_bit_cast(bf16x8, lb[(pt * 3u + 0u) * 64u + lane]);
-                bm[pt] = __builtin_bit_cast(bf16x8, lb[(pt * 3u + 1u) * 64u + lane]);
-                bl[pt] = __builtin_bit_cast(bf16x8, lb[(pt * 3u + 2u) * 64u + lane]);
-            }
+                for (uint32_t pt = 0; pt < 4; ++pt) {
+                    bh[pt] = __builtin_bit_cast(half8, lb[(pt * 2u + 0u) * 64u + lane]);
+                    bm[pt] = __builtin_bit_cast(half8, lb[(pt * 2u + 1u) * 64u + lane]);
+                }
 #pragma unroll
-            for (uint32_t r = 0; r < 2; ++r) {
-                const uint32_t rb = 2u * wave + r;
-                const bf16x8 a1 = __builtin_bit_cast(bf16x8, la[(rb * 3u + 0u) * 64u + lane]);
-                const bf16x8 a2 = __builtin_bit_cast(bf16x8, la[(rb * 3u + 1u) * 64u + lane]);
-                const bf16x8 a3 = __builtin_bit_cast(bf16x8, la[(rb * 3u + 2u) * 64u + lane]);
-                // Smallest products first, four independent accumulators
-                // between two updates of the same one.
+                for (uint32_t r = 0; r < 2; ++r) {
+                    const uint32_t rb = 2u * wave + r;
+                    const half8 a1 = __builtin_bit_cast(half8, la[(rb * 2u + 0u) * 64u + lane]);
+                    const half8 a2 = __builtin_bit_cast(half8, la[(rb * 2u + 1u) * 64u + lane]);
 #pragma unroll
-                for (uint32_t pt = 0; pt < 4; ++pt)
-                    acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bl[pt], acc[r][pt], 0, 0, 0);
+                    for (uint32_t pt = 0; pt < 4; ++pt)
+                        acc2[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, bm[pt], acc2[r][pt], 0, 0, 0);
 #pragma unroll
-                for (uint32_t pt = 0; pt < 4; ++pt)
-                    acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, bh[pt], acc[r][pt], 0, 0, 0);
+                    for (uint32_t pt = 0; pt < 4; ++pt)
+                        acc2[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, bh[pt], acc2[r][pt], 0, 0, 0);
 #pragma unroll
-                for (uint32_t pt = 0; pt < 4; ++pt)
-                    acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, bm[pt], acc[r][pt], 0, 0, 0);
+                    for (uint32_t pt = 0; pt < 4; ++pt)
+                        acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, bh[pt], acc[r][pt], 0, 0, 0);
+                }
+            } else {
+                bf16x8 bh[4], bm[4], bl[4];
 #pragma unroll
-                for (uint32_t pt = 0; pt < 4; ++pt)
-                    acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bm[pt], acc[r][pt], 0, 0, 0);
+                for (uint32_t pt = 0; pt < 4; ++pt) {
+                    bh[pt] = __builtin_bit_cast(bf16x8, lb[(pt * 3u + 0u) * 64u + lane]);
+                    bm[pt] = __builtin_bit_cast(bf16x8, lb[(pt * 3u + 1u) * 64u + lane]);
+                    bl[pt] = __builtin_bit_cast(bf16x8, lb[(pt * 3u + 2u) * 64u + lane]);
+                }
 #pragma unroll
-                for (uint32_t pt = 0; pt < 4; ++pt)
-                    acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, bh[pt], acc[r][pt], 0, 0, 0);
+                for (uint32_t r = 0; r < 2; ++r) {
+                    const uint32_t rb = 2u * wave + r;
+                    const bf16x8 a1 = __builtin_bit_cast(bf16x8, la[(rb * 3u + 0u) * 64u + lane]);
+                    const bf16x8 a2 = __builtin_bit_cast(bf16x8, la[(rb * 3u + 1u) * 64u + lane]);
+                    const bf16x8 a3 = __builtin_bit_cast(bf16x8, la[(rb * 3u + 2u) * 64u + lane]);
+                    // Smallest products first, four independent accumulators
+                    // between two updates of the same one.
 #pragma unroll
-                for (uint32_t pt = 0; pt < 4; ++pt)
-                    acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bh[pt], acc[r][pt], 0, 0, 0);
+                    for (uint32_t pt = 0; pt < 4; ++pt)
+                        acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bl[pt], acc[r][pt], 0, 0, 0);
+#pragma unroll
+                    for (uint32_t pt = 0; pt < 4; ++pt)
+                        acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, bh[pt], acc[r][pt], 0, 0, 0);
+#pragma unroll
+                    for (uint32_t pt = 0; pt < 4; ++pt)
+                        acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, bm[pt], acc[r][pt], 0, 0, 0);
+#pragma unroll
+                    for (uint32_t pt = 0; pt < 4; ++pt)
+                        acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bm[pt], acc[r][pt], 0, 0, 0);
+#pragma unroll
+                    for (uint32_t pt = 0; pt < 4; ++pt)
+                        acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, bh[pt], acc[r][pt], 0, 0, 0);
+#pragma unroll
+                    for (uint32_t pt = 0; pt < 4; ++pt)
+                        acc[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bh[pt], acc[r][pt], 0, 0, 0);
+                }
             }
         }
         // Step m + 1's A block into the buffer read in step m - 1 (every
@@ -609,6 +766,19 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
     // f = sum_k y_k^2: lane (column l % 16, group l / 16) holds rows
     // 4 (l / 16) + r of the wave's two row blocks for particle 16 pt + l % 16;
     // the four lane groups, then the eight waves, meet.
+    if constexpr (F16) {
+        // y = (sum h h + 2^-11 sum (h m + m h)) 2^-(e_k + e_d), row k of
+        // element i of acc[r][pt] being 16 (2 wave + r) + 4 (lane / 16) + i.
+        if (mine) {
+#pragma unroll
+            for (uint32_t r = 0; r < 2; ++r) {
+                const f4 rf = reinterpret_cast<const f4 *>(rfac)[4u * (2u * wave + r) + (lane >> 4)];
+#pragma unroll
+                for (uint32_t pt = 0; pt < 4; ++pt)
+                    acc[r][pt] = (acc[r][pt] + acc2[r][pt] * (1.0f / 2048.0f)) * rf;
+            }
+        }
+    }
     float fw[4];
 #pragma unroll
     for (uint32_t pt = 0; pt < 4; ++pt) {
@@ -649,23 +819,33 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
     wave_commit(S, t, blockIdx.x, key, improved ? 1u : 0u);
 }
 
+template <int NB, bool FULL_D, bool F16>
+static void launch_split(const SwarmDev &S, uint32_t t, dim3 grid, hipStream_t st, bool eq21)
+{
+    const dim3 block(512);
+    if (t == 0) {
+        if (eq21)
+            hipLaunchKernelGGL((k_dense3<NB, true, true, FULL_D, F16>), grid, block, 0, st, S, t);
+        else
+            hipLaunchKernelGGL((k_dense3<NB, false, true, FULL_D, F16>), grid, block, 0, st, S, t);
+    } else {
+        if (eq21)
+            hipLaunchKernelGGL((k_dense3<NB, true, false, FULL_D, F16>), grid, block, 0, st, S, t);
+        else
+            hipLaunchKernelGGL((k_dense3<NB, false, false, FULL_D, F16>), grid, block, 0, st, S, t);
+    }
+}
+
 template <int NB, bool FULL_D>
 static void launch_nbf(const SwarmDev &S, uint32_t t, dim3 grid, hipStream_t st)
 {
     const bool eq21 = S.order != 0;
+    if (S.a3 && S.split == SPLIT_F16X2) {
+        launch_split<NB, FULL_D, true>(S, t, grid, st, eq21);
+        return;
+    }
     if (S.a3) {
-        const dim3 block(512);
-        if (t == 0) {
-            if (eq21)
-                hipLaunchKernelGGL((k_dense3<NB, true, true, FULL_D>), grid, block, 0, st, S, t);
-            else
-                hipLaunchKernelGGL((k_dense3<NB, false, true, FULL_D>), grid, block, 0, st, S, t);
-        } else {
-            if (eq21)
-                hipLaunchKernelGGL((k_dense3<NB, true, false, FULL_D>), grid, block, 0, st, S, t);
-            else
-                hipLaunchKernelGGL((k_dense3<NB, false, false, FULL_D>), grid, block, 0, st, S, t);
-        }
+        launch_split<NB, FULL_D, false>(S, t, grid, st, eq21);
         return;
     }
     if (t == 0) {

@@ -122,6 +122,14 @@ void resolve(const sso_config &c, int *engine, int *storage)
     *storage = (c.storage == SSO_STORAGE_F32 || !packable) ? STORE_F32 : STORE_U24;
 }
 
+int resolve_contraction(const sso_config &c)
+{
+    if (c.kind != SSO_OBJ_DENSE || c.contraction == SSO_CONTRACT_F32) return SSO_CONTRACT_F32;
+    if (c.contraction == SSO_CONTRACT_BF16X3) return SSO_CONTRACT_BF16X3;
+    if (c.contraction == SSO_CONTRACT_F16X2) return SSO_CONTRACT_F16X2;
+    return dense_pack_f16x2(c.a, c.d, c.s, c.lo, c.hi, nullptr) ? SSO_CONTRACT_F16X2 : SSO_CONTRACT_BF16X3;
+}
+
 int validate(const sso_config *c, std::string *why)
 {
     const char *msg = "";
@@ -171,7 +179,10 @@ int validate_msg(const sso_config *c, const char **why)
         return bad(SSO_E_UNSUPPORTED, "the gradient polish needs the dense objective");
     if (!(c->polish_lr == c->polish_lr) || std::isinf(c->polish_lr)) return bad(SSO_E_INVAL, "polish_lr must be finite");
     if (c->storage < SSO_STORAGE_AUTO || c->storage > SSO_STORAGE_U24) return bad(SSO_E_INVAL, "unknown storage");
-    if (c->contraction < SSO_CONTRACT_AUTO || c->contraction > SSO_CONTRACT_BF16X3) return bad(SSO_E_INVAL, "unknown contraction");
+    if (c->contraction < SSO_CONTRACT_AUTO || c->contraction > SSO_CONTRACT_F16X2) return bad(SSO_E_INVAL, "unknown contraction");
+    if (c->kind == SSO_OBJ_DENSE && c->contraction == SSO_CONTRACT_F16X2 &&
+        !dense_pack_f16x2(c->a, c->d, c->s, c->lo, c->hi, nullptr))
+        return bad(SSO_E_INVAL, "the f16x2 contraction needs finite A and s with magnitudes within 2^+-100");
     if (c->storage == SSO_STORAGE_U24) {
         int e, st;
         resolve(*c, &e, &st);
@@ -309,6 +320,16 @@ int get_state(const SwarmDev &S, hipStream_t st, std::string *err, float *x, flo
 int set_state(const SwarmDev &S, hipStream_t st, uint64_t t, std::string *err, const float *x,
               const float *p, const float *fp)
 {
+    if (S.a3 && S.split == SPLIT_F16X2) {
+        // The fp16 split's scaling holds for differences x - s of positions
+        // inside the box.
+        const float hi = S.lo + S.span;
+        for (size_t k = 0; k < (size_t)S.n * S.d; ++k)
+            if (!(x[k] >= S.lo && x[k] <= hi && p[k] >= S.lo && p[k] <= hi)) {
+                *err = "with the f16x2 contraction every position must lie in [lo, hi]";
+                return SSO_E_INVAL;
+            }
+    }
     std::vector<uint32_t> rows((size_t)2 * S.buf, 0u);
     for (uint32_t i = 0; i < S.n; ++i) {
         if (!values_to_row(S, p + (size_t)i * S.d, rows.data() + (size_t)i * S.stride) ||

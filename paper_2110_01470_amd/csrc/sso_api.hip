@@ -57,12 +57,14 @@ struct Layout {
     int engine, storage;
 };
 
-// The DENSE generation kernel takes the split bf16 contraction unless the
-// FP32 one is asked for.
+// The DENSE generation kernel takes a split contraction (bf16 or fp16
+// parts of A in the workspace; the bf16 form is the larger) unless the FP32
+// one is asked for.
 bool split_contraction(const sso_config &c)
 {
     return c.kind == SSO_OBJ_DENSE && c.contraction != SSO_CONTRACT_F32;
 }
+static_assert(kRowAlign >= 32, "the fp16 split and its scales fit the bf16 split's region when dp >= 32");
 
 Layout make_layout(const sso_config &c)
 {
@@ -150,6 +152,7 @@ void bind_layout(const sso_config &c, const Layout &L, char *base, uint32_t lane
     S.a = c.kind == SSO_OBJ_DENSE ? (const float *)(base + L.a) : nullptr;
     S.at = c.kind == SSO_OBJ_DENSE ? (const float *)(base + L.at) : nullptr;
     S.a3 = split_contraction(c) ? (const uint16_t *)(base + L.a3) : nullptr;
+    S.split = resolve_contraction(c) == SSO_CONTRACT_F16X2 ? SPLIT_F16X2 : SPLIT_BF16X3;
     S.keys = (unsigned long long *)(base + L.keys);
     S.cnt = (uint32_t *)(base + L.cnt);
     S.sub = (unsigned long long *)(base + L.sub);
@@ -450,7 +453,10 @@ int sso_init(const sso_config *cfg, void *ws, size_t ws_bytes, void *stream, sso
                                hipMemcpyHostToDevice, ctx->stream);
         if (e == hipSuccess && S.a3) {
             a3pack.assign(dense_split_halves(d), 0);
-            dense_pack_split(cfg->a, d, a3pack.data());
+            if (S.split == SPLIT_F16X2)
+                (void)dense_pack_f16x2(cfg->a, d, cfg->s, cfg->lo, cfg->hi, a3pack.data());  // fits: resolved so
+            else
+                dense_pack_split(cfg->a, d, a3pack.data());
             e = hipMemcpyAsync((void *)S.a3, a3pack.data(), sizeof(uint16_t) * a3pack.size(),
                                hipMemcpyHostToDevice, ctx->stream);
         }
@@ -601,12 +607,16 @@ const char *sso_strerror(int code)
 
 const char *sso_last_error(const sso_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
 
-int sso_get_mapping(const sso_ctx *ctx, int *engine_out, int *storage_out, uint32_t *lanes_out)
+int sso_get_mapping(const sso_ctx *ctx, int *engine_out, int *storage_out, uint32_t *lanes_out,
+                    int *contraction_out)
 {
     if (!ctx) return SSO_E_INVAL;
     if (engine_out) *engine_out = ctx->engine;
     if (storage_out) *storage_out = ctx->storage == STORE_U24 ? SSO_STORAGE_U24 : SSO_STORAGE_F32;
     if (lanes_out) *lanes_out = ctx->S.lanes;
+    if (contraction_out)
+        *contraction_out = !ctx->S.a3 ? SSO_CONTRACT_F32
+                                      : ctx->S.split == SPLIT_F16X2 ? SSO_CONTRACT_F16X2 : SSO_CONTRACT_BF16X3;
     return SSO_OK;
 }
 

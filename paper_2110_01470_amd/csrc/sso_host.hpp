@@ -38,6 +38,9 @@ int validate(const sso_config *c, std::string *why);
 int validate_msg(const sso_config *c, const char **why);
 // Engine and row storage a valid configuration resolves to.
 void resolve(const sso_config &c, int *engine, int *storage);
+// The dense kernel's contraction (SSO_CONTRACT_F32, _BF16X3 or _F16X2) for a
+// valid configuration; F32 for the other objectives.
+int resolve_contraction(const sso_config &c);
 int hip_fail(std::string *err, hipError_t e, const char *what);
 
 // Integer thresholds of Eq. (2.1) in the configured order, the fresh-draw

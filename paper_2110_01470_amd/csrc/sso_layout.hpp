@@ -32,6 +32,9 @@ inline bool is_paper_kind(int kind) { return kind >= OBJ_F1 && kind <= OBJ_F9; }
 //   w0 = u0 | u1 << 24,  w1 = u1 >> 8 | u2 << 16,  w2 = u2 >> 16 | u3 << 8,
 // which moves 9 bytes per variable and generation instead of 12.
 enum { STORE_F32 = 0, STORE_U24 = 1 };
+// The dense kernel's contraction when a split copy of A is held: three
+// exact bf16 parts, or two scaled fp16 parts (gen_dense.hip).
+enum { SPLIT_BF16X3 = 0, SPLIT_F16X2 = 1 };
 enum : uint32_t { ST_ROW = 1u, ST_ALIAS = 2u };
 
 constexpr uint32_t kRowAlign = 32;      // floats per row alignment unit (128 B)
@@ -65,7 +68,7 @@ struct SwarmDev {
     const float *w;              // [dp] ripple weights, zero padded (or null)
     const float *a;              // dense matrix, layout of the dense kernel (or null)
     const float *at;             // its transpose in the same layout (dense only)
-    const uint16_t *a3;          // dense matrix split into three bf16 parts (split contraction), or null
+    const uint16_t *a3;          // dense matrix split into bf16 or fp16 parts (split contraction), or null
     unsigned long long *keys;    // [trace_cap] gBest key per finished generation (ring)
     uint32_t *cnt;               // [trace_cap] improved pBests per finished generation (ring)
     unsigned long long *sub;     // [kGroups][kSubSlots][kSubStride]: key, then count
@@ -80,6 +83,7 @@ struct SwarmDev {
     int32_t kind, order;
     uint32_t nsub;               // sub-slots in use (a power of two <= kSubSlots)
     uint32_t lanes;              // lanes per particle (batched kernel; a power of two)
+    int32_t split;               // SPLIT_BF16X3 or SPLIT_F16X2 (with a3)
 };
 
 // Batched engine: many independent separable swarms advance together, one
@@ -108,6 +112,7 @@ int launch_resident(const SwarmDev &S, uint32_t t_first, uint32_t generations, v
 bool resident_fits(uint32_t n, uint32_t d, int kind);
 uint64_t dense_matrix_floats(uint32_t d);
 uint64_t dense_split_halves(uint32_t d);  // bf16 values of the split matrix
+uint64_t dense_f16x2_halves(uint32_t d);  // 16-bit words of the fp16 split (parts and scales)
 
 int launch_batch_fill(const BatchDev &B, void *stream);    // every swarm's trace ring and sub-slots
 int launch_batch_init(const BatchDev &B, void *stream);    // generation 0 of every swarm
@@ -121,6 +126,11 @@ int launch_batch_collect(const BatchDev &B, uint32_t t, void *stream);
 size_t batch_stage_bytes(int kind, int storage, uint32_t chunks);
 void dense_pack_matrix(const float *a, uint32_t d, float *out);
 void dense_pack_split(const float *a, uint32_t d, uint16_t *out);
+// The fp16 split of A with its scales for differences x - s within the box
+// [lo, hi]; false (nothing written) if the instance does not fit the scaling
+// (a non-finite value, or magnitudes beyond 2^+-100).  out may be null to
+// check only.
+bool dense_pack_f16x2(const float *a, uint32_t d, const float *s, float lo, float hi, uint16_t *out);
 
 // Dense objective at given points and its gradient (grad_dense.hip).
 struct GradArgs {

@@ -78,6 +78,31 @@ def test_split_contraction_adds_the_bf16_parts_of_a(d):
     assert binding.workspace_bytes(cs) == binding.workspace_bytes(cf)
 
 
+def test_f16x2_contraction_needs_a_scalable_instance():
+    """The fp16 split scales each row of A and the differences x - s by
+    powers of two into fp16's range; instances it cannot scale (a
+    non-finite entry, magnitudes beyond 2^+-100) are refused when asked for
+    explicitly, and AUTO then takes the bf16 split (same workspace)."""
+    d = 64
+    rng = np.random.Generator(np.random.PCG64(5))
+    a = (rng.standard_normal((d, d)) / 8).astype(np.float32)
+    good, k1 = cfg(n=100, d=d, kind="dense", a=a, contraction="f16x2")
+    b3, k2 = cfg(n=100, d=d, kind="dense", a=a, contraction="bf16x3")
+    assert binding.workspace_bytes(good) == binding.workspace_bytes(b3) > 0
+    for bad_a in (np.where(np.eye(d) > 0, np.float32(np.inf), a).astype(np.float32),
+                  (a * np.float32(1e35)).astype(np.float32),
+                  (a * np.float32(1e-33)).astype(np.float32)):
+        c, k3 = cfg(n=100, d=d, kind="dense", a=bad_a, contraction="f16x2")
+        with pytest.raises(binding.SSOError):
+            binding.workspace_bytes(c)
+        c, k4 = cfg(n=100, d=d, kind="dense", a=bad_a)
+        assert binding.workspace_bytes(c) == binding.workspace_bytes(b3)
+    # A box far beyond the shift: differences up to 3e35.
+    c, k5 = cfg(n=100, d=d, kind="dense", a=a, lo=-3e35, hi=3e35, contraction="f16x2")
+    with pytest.raises(binding.SSOError):
+        binding.workspace_bytes(c)
+
+
 @pytest.mark.parametrize("kw", [
     dict(n=0), dict(d=0), dict(lo=1.0, hi=1.0), dict(lo=float("nan")),
     dict(cg=0.8), dict(cp=0.95), dict(cw=1.0 - 2.0 ** -8), dict(cw=1.5),
@@ -91,7 +116,7 @@ def test_split_contraction_adds_the_bf16_parts_of_a(d):
     dict(polish_every=50, polish_steps=5), dict(kind="ripple", w=np.ones(30, np.float32), polish_every=1),
     dict(kind="dense", a=np.eye(30, dtype=np.float32), polish_lr=float("nan")),
     dict(storage="u24", kind="dense", a=np.eye(30, dtype=np.float32)),
-    dict(contraction=3), dict(contraction=-1),
+    dict(contraction=4), dict(contraction=-1),
 ])
 def test_invalid_configs_are_rejected(kw):
     c, keep = cfg(**kw)

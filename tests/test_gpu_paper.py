@@ -168,7 +168,7 @@ def test_auto_engine_choice(kind, n, d, want):
         s = np.zeros(d, np.float32)
         w = np.ones(d, np.float32) if kind == "ripple" else None
     sw = Swarm(n, d, kind, lo, hi, 0.8, 0.6, 0.3, 7, s, w, order=oracle.ORDER_EQ21)
-    assert sw.mapping() == want
+    assert sw.mapping()[:3] == want
     sw.run(2)
     assert sw.best()[3] == 2
     sw.close()

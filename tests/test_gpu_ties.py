@@ -46,11 +46,12 @@ CASES = [
     # 100 -> 1, 1536 -> 24, 4111 -> 64 -> 0, 16000 -> 250 -> 58
     ("dense", 16384, 256, (-10.0, 10.0), dict(contraction="bf16x3"), [100, 1536, 4111, 16000], [3, 57]),
     ("dense", 16384, 256, (-10.0, 10.0), dict(contraction="f32"), [100, 1536, 4111, 16000], [3, 57]),
+    ("dense", 16384, 256, (-10.0, 10.0), dict(contraction="f16x2"), [100, 1536, 4111, 16000], [3, 57]),
 ]
 
 
 @pytest.mark.parametrize("case", range(len(CASES)), ids=["ripple_u24", "ripple_f32", "dense_split",
-                                                          "dense_f32"])
+                                                          "dense_f32", "dense_f16x2"])
 def test_ties_nan_and_signed_zero_across_workgroups(case):
     kind, n, d, (lo, hi), extra, tied, nans = CASES[case]
     s, w, a = grid_shift(kind, d, lo, hi, 17 + case)
