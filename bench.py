@@ -70,9 +70,14 @@ def measured_traffic(wl, window=None, key=None):
     of generations than the line times."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            rec = json.load(fh).get(key or wl.name)
+            recs = json.load(fh)
     except (OSError, ValueError):
         return None
+    key = key or wl.name
+    rec = recs.get(key)
+    if rec and window is not None and rec.get("timed_generations") != list(window):
+        # A record of the same kernel over another window of the run.
+        rec = recs.get(f"{key}@{window[0]}-{window[1]}")
     kind = "batch" if hasattr(wl, "count") else wl.kind
     if not rec or rec.get("kernel_hash") != kernel_hash(kind):
         return None
