@@ -457,20 +457,19 @@ bool dense_pack_f16x2(const float *a, uint32_t d, const float *s, float lo, floa
 // the other selects or waits.
 //   Select: thread (particle pl = tid / 8, q = tid % 8) selects chunk
 //   8 m + q of its particle in step m (Eq. 2.1), writes it, and writes the
-//   three bf16 parts of d = x' - s into LDS in the B-operand layout: tile
-//   pl / 16, lane (pl % 16) + 16 (q / 2), elements 4 (q % 2) .. 4 (q % 2) + 3.
+//   parts of d = x' - s (three bf16, or two scaled fp16) into LDS in the
+//   B-operand layout: tile pl / 16, lane (pl % 16) + 16 (q / 2), elements
+//   4 (q % 2) .. 4 (q % 2) + 3.
 //   Contract: wave w owns row blocks 2 w and 2 w + 1 of A for all four tiles
-//   of 16 particles: per step it reads 6 A operands (its row blocks, three
-//   parts) and 12 B operands (four tiles, three parts) from LDS for 48
-//   MFMAs (a wave owning all 256 rows of 16 particles would read 48 A
-//   operands for 96).
+//   of 16 particles: per step it takes its A operands (its row blocks, every
+//   part) from global memory straight into registers -- no other wave uses
+//   them, so they would only pass through LDS (8 % faster without) -- and
+//   reads the B operands of all four tiles from LDS.
 //   Fitness: each wave's partial sum of y_k^2 over its 32 rows per particle
 //   meets the others' in LDS, added in wave order.
-// One barrier per step: step m + 1's A block and d parts are written during
-// step m into the buffers not read in step m.  A reaches LDS through
-// registers (plain loads, then LDS stores): with a global-to-LDS copy in
-// flight the compiler waits for every outstanding load before it uses any
-// loaded register, which would drain the prefetch of later steps each step.
+// One barrier per step: step m + 1's d parts are written during step m into
+// the buffer not read in step m; step m + 1's A operands are requested at
+// the start of step m into the register set not used in step m.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
@@ -508,12 +507,7 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
 {
     constexpr uint32_t PARTS = F16 ? 2u : 3u;
     constexpr uint32_t STEPS = NB / 2;              // 32 variables per step
-    constexpr uint32_t STEP_U = NB * PARTS * 64u;   // 16-byte units of A per step
-    constexpr uint32_t PER = (STEP_U + 511u) / 512u;
-    constexpr bool FULL = STEP_U % 512u == 0;
     constexpr uint32_t B_U = 4u * PARTS * 64u;      // 16-byte units of d parts per step
-    __shared__ f4 lda0[STEP_U];
-    __shared__ f4 lda1[STEP_U];
     __shared__ f4 ldb0[B_U];
     __shared__ f4 ldb1[B_U];
     __shared__ float fpart[8][64];
@@ -549,26 +543,24 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
     const size_t ioff = (size_t)ie * S.stride;
     const f4 *s4 = reinterpret_cast<const f4 *>(S.s);
 
-    // Step m's block of A parts: loaded into registers, written to LDS
-    // buffer b later.
-    f4 ra[PER];
-    auto load_a = [&](uint32_t m) {
+    const bool mine = NB >= 16 || 2u * wave < (uint32_t)NB;  // this wave owns row blocks
+    // This wave's A operands of step m -- row blocks 2 wave and 2 wave + 1,
+    // every part, 16 bytes per lane in the MFMA layout -- straight from
+    // global memory (L2) into register set b: no other wave of the
+    // workgroup reads them, so they take no LDS.
+    f4 aop[2][2][PARTS];
+    auto load_aop = [&](uint32_t m, uint32_t b) {
+        if (mine) {
 #pragma unroll
-        for (uint32_t r = 0; r < PER; ++r) {
-            const uint32_t u = tid + r * 512u;
-            if (FULL || u < STEP_U) ra[r] = a_pack[(size_t)m * STEP_U + u];
+            for (uint32_t r = 0; r < 2; ++r)
+#pragma unroll
+                for (uint32_t p = 0; p < PARTS; ++p)
+                    aop[b][r][p] = a_pack[(((size_t)m * NB + 2u * wave + r) * PARTS + p) * 64u + lane];
         }
     };
-    auto store_a = [&](uint32_t b) {
-        f4 *dst = b ? lda1 : lda0;
-#pragma unroll
-        for (uint32_t r = 0; r < PER; ++r) {
-            const uint32_t u = tid + r * 512u;
-            if (FULL || u < STEP_U) dst[u] = ra[r];
-        }
-    };
-    // A block 0 does not depend on gBest: requested before the key arrives.
-    load_a(0);
+    // Step 0's operands do not depend on gBest: requested before the key
+    // arrives.
+    load_aop(0, 0);
     const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
     // Operands of the select, two steps' worth: set m & 1 holds step m's
     // pBest, position, gBest and shift chunks.
@@ -618,7 +610,6 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
         prefetch_g(0, 0);
         if (STEPS > 1) prefetch_g(1, 1);
     }
-    store_a(0);
 
     // Select (Eq. 2.1) step m's chunk from set b and write the three bf16
     // parts of d = x' - s into d-part buffer `db`.
@@ -666,7 +657,6 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
     for (uint32_t r = 0; r < 2; ++r)
 #pragma unroll
         for (uint32_t pt = 0; pt < 4; ++pt) acc[r][pt] = zero4;
-    const bool mine = NB >= 16 || 2u * wave < (uint32_t)NB;  // this wave owns row blocks
     // F16X2: the cross products h m + m h, scaled by 2^-11 at the end.
     f4 acc2[2][4];
 #pragma unroll
@@ -674,13 +664,13 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
 #pragma unroll
         for (uint32_t pt = 0; pt < 4; ++pt) acc2[r][pt] = zero4;
 
-    __syncthreads();  // A block 0 and step 0's d parts are in LDS
+    __syncthreads();  // step 0's d parts are in LDS
 
 #pragma unroll
     for (uint32_t m = 0; m < STEPS; ++m) {
         const uint32_t cur = m & 1u;
         const bool more = m + 1 < STEPS;
-        if (more) load_a(m + 1);
+        if (more) load_aop(m + 1, cur ^ 1u);
         if (m + 2 < STEPS) {
             prefetch_own(m + 2, cur);
             prefetch_g(m + 2, cur);
@@ -688,7 +678,6 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
         __builtin_amdgcn_sched_barrier(0);
         if (more) select_step(m + 1, cur ^ 1u, cur ? ldb0 : ldb1);
         if (mine) {
-            const f4 *la = cur ? lda1 : lda0;
             const f4 *lb = cur ? ldb1 : ldb0;
             if constexpr (F16) {
                 half8 bh[4], bm[4];
@@ -699,9 +688,8 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
                 }
 #pragma unroll
                 for (uint32_t r = 0; r < 2; ++r) {
-                    const uint32_t rb = 2u * wave + r;
-                    const half8 a1 = __builtin_bit_cast(half8, la[(rb * 2u + 0u) * 64u + lane]);
-                    const half8 a2 = __builtin_bit_cast(half8, la[(rb * 2u + 1u) * 64u + lane]);
+                    const half8 a1 = __builtin_bit_cast(half8, aop[cur][r][0]);
+                    const half8 a2 = __builtin_bit_cast(half8, aop[cur][r][1]);
 #pragma unroll
                     for (uint32_t pt = 0; pt < 4; ++pt)
                         acc2[r][pt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, bm[pt], acc2[r][pt], 0, 0, 0);
@@ -722,10 +710,9 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
                 }
 #pragma unroll
                 for (uint32_t r = 0; r < 2; ++r) {
-                    const uint32_t rb = 2u * wave + r;
-                    const bf16x8 a1 = __builtin_bit_cast(bf16x8, la[(rb * 3u + 0u) * 64u + lane]);
-                    const bf16x8 a2 = __builtin_bit_cast(bf16x8, la[(rb * 3u + 1u) * 64u + lane]);
-                    const bf16x8 a3 = __builtin_bit_cast(bf16x8, la[(rb * 3u + 2u) * 64u + lane]);
+                    const bf16x8 a1 = __builtin_bit_cast(bf16x8, aop[cur][r][0]);
+                    const bf16x8 a2 = __builtin_bit_cast(bf16x8, aop[cur][r][1]);
+                    const bf16x8 a3 = __builtin_bit_cast(bf16x8, aop[cur][r][PARTS - 1]);
                     // Smallest products first, four independent accumulators
                     // between two updates of the same one.
 #pragma unroll
@@ -749,13 +736,10 @@ __global__ __launch_bounds__(512) void k_dense3(SwarmDev S, uint32_t t)
                 }
             }
         }
-        // Step m + 1's A block into the buffer read in step m - 1 (every
-        // wave passed that step's barrier), after this step's MFMAs.
         __builtin_amdgcn_sched_barrier(0);
-        if (more) store_a(cur ^ 1u);
-        // The LDS writes of this step (A block, d parts) are visible and this
-        // wave's LDS reads of the buffers the next step overwrites are done
-        // before the barrier; loads of later steps stay in flight.
+        // The LDS writes of this step (the next step's d parts) are visible
+        // and this wave's LDS reads of the buffer the next step overwrites are
+        // done before the barrier; loads of later steps stay in flight.
         // (lgkmcnt is bits 11:8; vmcnt 3:0 and 15:14, expcnt 6:4 at maxima.)
         __builtin_amdgcn_s_waitcnt(0xC07Fu);  // lgkmcnt(0)
         __builtin_amdgcn_sched_barrier(0);
