@@ -55,37 +55,10 @@ static int launch_k(const SwarmDev &S, uint32_t t, uint32_t lanes, hipStream_t s
     }
 }
 
-// Table 3.2's functions: one kernel per (order, storage), the function and
-// the lane count (S.lanes) taken at run time, rows staged (d <= 1024).
-template <bool EQ21, class Store>
-static int launch_paper_s(const SwarmDev &S, uint32_t t, hipStream_t st)
-{
-    const uint32_t per_block = kWaves * (64u / S.lanes);
-    const uint32_t blocks = (S.n + per_block - 1) / per_block;
-    const size_t lds = stage_bytes<OBJ_PAPER, Store>(S);
-    if (t == 0)
-        hipLaunchKernelGGL((k_stream<OBJ_PAPER, 0, EQ21, true, true, true, Store>), dim3(blocks),
-                           dim3(64 * kWaves), lds, st, S, t);
-    else
-        hipLaunchKernelGGL((k_stream<OBJ_PAPER, 0, EQ21, false, true, true, Store>), dim3(blocks),
-                           dim3(64 * kWaves), lds, st, S, t);
-    return (int)hipGetLastError();
-}
-
-static int launch_paper(const SwarmDev &S, uint32_t t, hipStream_t st)
-{
-    if (S.chunks > kStageMaxChunks || S.lanes == 0 || S.lanes > 64 || (S.lanes & (S.lanes - 1)))
-        return (int)hipErrorInvalidValue;
-    const bool eq21 = S.order != 0;
-    if (S.storage == STORE_U24)
-        return eq21 ? launch_paper_s<true, StoreU24>(S, t, st) : launch_paper_s<false, StoreU24>(S, t, st);
-    return eq21 ? launch_paper_s<true, StoreF32>(S, t, st) : launch_paper_s<false, StoreF32>(S, t, st);
-}
-
 int launch_stream_generation(const SwarmDev &S, uint32_t t, uint32_t lanes, void *stream)
 {
     hipStream_t st = (hipStream_t)stream;
-    if (is_paper_kind(S.kind)) return launch_paper(S, t, st);
+    if (is_paper_kind(S.kind)) return launch_stream_paper(S, t, st);
     const bool eq21 = S.order != 0;
     if (S.kind == OBJ_SPHERE)
         return eq21 ? launch_k<OBJ_SPHERE, true>(S, t, lanes, st)

@@ -20,10 +20,9 @@
 namespace sso {
 
 enum { OBJ_SPHERE = 0, OBJ_RIPPLE = 1, OBJ_DENSE = 2 };
-// Table 3.2's benchmark functions (values of sso_objective), and the tag of
-// the one STREAM kernel that evaluates all of them.
-enum { OBJ_F1 = 11, OBJ_F9 = 19, OBJ_PAPER = 3 };
-inline bool is_paper_kind(int kind) { return kind >= OBJ_F1 && kind <= OBJ_F9; }
+// Table 3.2's benchmark functions (values of sso_objective).
+enum { OBJ_F1 = 11, OBJ_F9 = 19 };
+constexpr bool is_paper_kind(int kind) { return kind >= OBJ_F1 && kind <= OBJ_F9; }
 
 // Row storage.  F32: dp floats per row, a float4 per chunk of 4 variables.
 // U24: every position is a point of the draw grid lo + u span 2^-24 with a
@@ -105,6 +104,7 @@ struct BatchDev {
 
 // Launchers (each returns hipSuccess or the launch error).
 int launch_stream_generation(const SwarmDev &S, uint32_t t, uint32_t lanes, void *stream);
+int launch_stream_paper(const SwarmDev &S, uint32_t t, void *stream);  // Table 3.2's functions
 int launch_dense_generation(const SwarmDev &S, uint32_t t, void *stream);
 int launch_fill_trace(const SwarmDev &S, void *stream);  // clears trace ring and sub-slot groups
 int launch_debug_rng(const SwarmDev &S, uint32_t t, uint32_t *out, void *stream);

@@ -45,7 +45,7 @@ __device__ __forceinline__ uint32_t gbest_guess_low(const SwarmDev &S, uint32_t 
 // Shift and weight arrays staged in LDS: ripple both, sphere the shift,
 // Table 3.2's functions neither.
 template <int KIND>
-constexpr uint32_t staged_arrays() { return KIND == OBJ_RIPPLE ? 2u : KIND == OBJ_PAPER ? 0u : 1u; }
+constexpr uint32_t staged_arrays() { return KIND == OBJ_RIPPLE ? 2u : is_paper_kind(KIND) ? 0u : 1u; }
 
 template <int KIND, class Store>
 inline size_t stage_bytes(const SwarmDev &S)
@@ -134,7 +134,7 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
 
     // Loads that do not depend on gBest go out before the start-of-generation
     // barrier: the shift and weights for staging.
-    if constexpr (STAGE && KIND != OBJ_PAPER) {
+    if constexpr (STAGE && !is_paper_kind(KIND)) {
         for (uint32_t q = tid; q < S.chunks; q += blockDim.x) {
             ls[q] = s4[q];
             if (KIND == OBJ_RIPPLE) lw[q] = w4[q];
@@ -212,8 +212,8 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
             }
             Store::store(xrow_ptr, c, xn);
             const f4 xf = Store::value(S, xn);
-            if constexpr (KIND == OBJ_PAPER) {
-                paper_chunk(pacc, xf, c, S.d, L, ln, S.kind);
+            if constexpr (is_paper_kind(KIND)) {
+                paper_chunk(pacc, xf, c, S.d, L, ln, KIND);
             } else {
                 const f4 sv = STAGE ? ls[c] : s4[c];
                 const f4 wv = (KIND == OBJ_RIPPLE) ? (STAGE ? lw[c] : w4[c]) : zero;
@@ -226,8 +226,8 @@ __device__ __forceinline__ void stream_body(const SwarmDev &S, uint32_t t, uint3
     }
     // Butterfly over the L lanes of the particle (the masks are immediates;
     // with a runtime width the steps above it are skipped uniformly).
-    if constexpr (KIND == OBJ_PAPER) {
-        acc = paper_finish(pacc, L, S.d, S.kind);
+    if constexpr (is_paper_kind(KIND)) {
+        acc = paper_finish(pacc, L, S.d, KIND);
     } else {
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1)

@@ -143,20 +143,21 @@ def test_resident_single_launch_against_oracle():
 
 
 @pytest.mark.parametrize("kind,n,d,want", [("f4", 100, 50, ("resident", "f32", 16)),
-                                           ("f4", 256, 50, ("resident", "f32", 16)),
-                                           ("f4", 257, 50, ("stream", "u24", 16)),
+                                           ("f4", 240, 50, ("resident", "f32", 16)),
+                                           ("f4", 241, 50, ("stream", "u24", 16)),
                                            ("f4", 350, 50, ("stream", "u24", 16)),
-                                           ("f6", 144, 50, ("resident", "f32", 16)),
-                                           ("f6", 145, 50, ("stream", "u24", 16)),
-                                           ("f3", 208, 50, ("resident", "f32", 16)),
+                                           ("f6", 128, 50, ("resident", "f32", 16)),
+                                           ("f6", 129, 50, ("stream", "u24", 16)),
+                                           ("f3", 192, 50, ("resident", "f32", 16)),
+                                           ("f3", 193, 50, ("stream", "u24", 16)),
                                            ("f5", 177, 50, ("stream", "u24", 16)),
                                            ("f1", 30, 130, ("resident", "f32", 64)),
                                            ("sphere", 100, 30, ("resident", "f32", 8)),
                                            ("ripple", 4096, 1000, ("stream", "u24", 32))])
 def test_auto_engine_choice(kind, n, d, want):
     """AUTO takes the one-workgroup engine for Table 3.2's functions up to
-    a per-function number of waves of particles per SIMD (N L / 256: 16 for
-    f4, 9 for f6, 13 for f3, 11 for f5), STREAM beyond; the context reports
+    a per-function number of waves of particles per SIMD (N L / 256: 15 for
+    f4, 8 for f6, 12 for f3, 11 for f5), STREAM beyond; the context reports
     what it resolved to."""
     from paper_2110_01470_amd.binding import Swarm
 
