@@ -431,25 +431,31 @@ def main():
                     "achieved_tflops": t32, "frac_of_fp32_matrix_peak": t32 / FP32_MATRIX_PEAK_TFLOPS,
                     "traffic": measured_traffic(wl, window, wl.name + "/f32")}
         log(f"gpu, FP32 contraction: {ms32:.3f} ms for {steps} generations")
-    if split:
-        # A split contraction runs six bf16 (BF16X3) or three fp16 (F16X2)
-        # products per FP32 product on the 16-bit matrix cores (the same
-        # dense peak for both types): priced at their work and that peak.  The
-        # FP32-equivalent rate against the FP32 matrix peak is given beside it.
-        products = 3 if contraction == "f16x2" else 6
+    if wl.kind == "dense":
+        # Two roofs: the contraction's FLOP against its matrix peak, and the
+        # 12 B per update of rows against HBM.  A split contraction runs six
+        # bf16 (BF16X3) or three fp16 (F16X2) products per FP32 product on the
+        # 16-bit matrix cores (the same dense peak for both types), priced at
+        # that work; the FP32-equivalent rate against the FP32 matrix peak is
+        # given beside it.  The line's bound is the roof whose ideal time is
+        # the longer one; the other roof rides along in "other_roof".
+        products = (3 if contraction == "f16x2" else 6) if split else 1
+        peak = BF16_MATRIX_PEAK_TFLOPS if split else FP32_MATRIX_PEAK_TFLOPS
         flop = products * 2.0 * wl.n * wl.d * wl.d
-        achieved = flop / (ms_per_step / 1e3) / 1e12
-        fp32_eq = achieved / products / FP32_MATRIX_PEAK_TFLOPS
-        roofline = {"bound": "mfma", "achieved": achieved, "peak": BF16_MATRIX_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / BF16_MATRIX_PEAK_TFLOPS,
-                    "traffic": measured_traffic(wl, window, wl.name + "/" + contraction),
-                    "fp32_equivalent_frac": fp32_eq}
-    elif wl.kind == "dense":
-        flop = 2.0 * wl.n * wl.d * wl.d
-        achieved = flop / (ms_per_step / 1e3) / 1e12
-        roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MATRIX_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / FP32_MATRIX_PEAK_TFLOPS,
-                    "traffic": measured_traffic(wl, window, wl.name + "/f32")}
+        tflops = flop / (ms_per_step / 1e3) / 1e12
+        mfma_roof = {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
+                     "frac": tflops / peak}
+        byt = BYTES_PER_UPDATE * wl.n * wl.d
+        gbs = byt / (ms_per_step / 1e3) / 1e9
+        hbm_roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS}
+        hbm_binds = byt / (HBM_PEAK_GBS * 1e9) >= flop / (peak * 1e12)
+        roofline, other = (hbm_roof, mfma_roof) if hbm_binds else (mfma_roof, hbm_roof)
+        roofline = dict(roofline)
+        roofline["traffic"] = measured_traffic(wl, window, wl.name + "/" + contraction)
+        if split:
+            roofline["fp32_equivalent_frac"] = tflops / products / FP32_MATRIX_PEAK_TFLOPS
+        roofline["other_roof"] = other
     else:
         byt = BYTES_PER_UPDATE * wl.n * wl.d
         achieved = byt / (ms_per_step / 1e3) / 1e9
