@@ -1,15 +1,16 @@
 // STREAM engine for Table 3.2's functions: one fused kernel per generation,
-// specialised per (function, order, storage); the lane count (S.lanes) is
-// taken at run time and rows are staged (d <= 1024).  The body is in
-// stream_body.hpp.
+// specialised per (function, order, storage) and, for the generations after
+// the initialisation, per lane count 8, 16, 32 or 64 (LT; any other count and
+// the initialisation take S.lanes at run time).  Rows are staged (d <= 1024).
+// The body is in stream_body.hpp.
 #include "stream_body.hpp"
 
 namespace sso {
 
-template <int KIND, bool EQ21, bool INIT, class Store>
+template <int KIND, bool EQ21, bool INIT, class Store, int LT>
 __global__ __launch_bounds__(64 * kWaves) void k_stream_paper(SwarmDev S, uint32_t t)
 {
-    stream_body<KIND, 0, EQ21, INIT, true, true, Store>(S, t, blockIdx.x, S.lanes);
+    stream_body<KIND, LT, EQ21, INIT, true, true, Store>(S, t, blockIdx.x, LT ? (uint32_t)LT : S.lanes);
 }
 
 template <int KIND, bool EQ21, class Store>
@@ -18,12 +19,18 @@ static int launch_kind(const SwarmDev &S, uint32_t t, hipStream_t st)
     const uint32_t per_block = kWaves * (64u / S.lanes);
     const uint32_t blocks = (S.n + per_block - 1) / per_block;
     const size_t lds = stage_bytes<KIND, Store>(S);
-    if (t == 0)
-        hipLaunchKernelGGL((k_stream_paper<KIND, EQ21, true, Store>), dim3(blocks), dim3(64 * kWaves),
-                           lds, st, S, t);
-    else
-        hipLaunchKernelGGL((k_stream_paper<KIND, EQ21, false, Store>), dim3(blocks), dim3(64 * kWaves),
-                           lds, st, S, t);
+    const dim3 grid(blocks), block(64 * kWaves);
+    if (t == 0) {
+        hipLaunchKernelGGL((k_stream_paper<KIND, EQ21, true, Store, 0>), grid, block, lds, st, S, t);
+    } else {
+        switch (S.lanes) {
+        case 8: hipLaunchKernelGGL((k_stream_paper<KIND, EQ21, false, Store, 8>), grid, block, lds, st, S, t); break;
+        case 16: hipLaunchKernelGGL((k_stream_paper<KIND, EQ21, false, Store, 16>), grid, block, lds, st, S, t); break;
+        case 32: hipLaunchKernelGGL((k_stream_paper<KIND, EQ21, false, Store, 32>), grid, block, lds, st, S, t); break;
+        case 64: hipLaunchKernelGGL((k_stream_paper<KIND, EQ21, false, Store, 64>), grid, block, lds, st, S, t); break;
+        default: hipLaunchKernelGGL((k_stream_paper<KIND, EQ21, false, Store, 0>), grid, block, lds, st, S, t);
+        }
+    }
     return (int)hipGetLastError();
 }
 
