@@ -1,8 +1,8 @@
 // STREAM engine for Table 3.2's functions: one fused kernel per generation,
 // specialised per (function, order, storage) and, for the generations after
-// the initialisation, per lane count 8, 16, 32 or 64 (LT; any other count and
-// the initialisation take S.lanes at run time).  Rows are staged (d <= 1024).
-// The body is in stream_body.hpp.
+// the initialisation, per lane count LT = 8, 16, 32 or 64 (the counts a swarm
+// can have); the initialisation takes S.lanes at run time.  Rows are staged
+// (d <= 1024).  The body is in stream_body.hpp.
 #include "stream_body.hpp"
 
 namespace sso {
@@ -28,7 +28,7 @@ static int launch_kind(const SwarmDev &S, uint32_t t, hipStream_t st)
         case 16: hipLaunchKernelGGL((k_stream_paper<KIND, EQ21, false, Store, 16>), grid, block, lds, st, S, t); break;
         case 32: hipLaunchKernelGGL((k_stream_paper<KIND, EQ21, false, Store, 32>), grid, block, lds, st, S, t); break;
         case 64: hipLaunchKernelGGL((k_stream_paper<KIND, EQ21, false, Store, 64>), grid, block, lds, st, S, t); break;
-        default: hipLaunchKernelGGL((k_stream_paper<KIND, EQ21, false, Store, 0>), grid, block, lds, st, S, t);
+        default: return (int)hipErrorInvalidValue;
         }
     }
     return (int)hipGetLastError();
