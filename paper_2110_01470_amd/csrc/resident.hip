@@ -111,17 +111,20 @@ __device__ __forceinline__ float paper_fitness(PaperAcc q, uint32_t L, uint32_t 
 // posts never overwrite the ones the previous generation is still reading
 // (every read of buffer b happens before the reader's next barrier, every
 // later write of b after it).  The lane sums are those of paper_finish with
-// the short distances as DPP moves (lane_fold).
-template <int KIND, bool EQ21, int P>
+// the short distances as DPP moves (lane_fold).  The lane count LT (8, 16, 32
+// or 64, the STREAM engine's for the swarm) is a template parameter, so the
+// folds and lane masks are constants.
+template <int KIND, bool EQ21, int P, int LT>
 __global__ __launch_bounds__(kResidentMaxThreads) void k_resident_paper(SwarmDev S, uint32_t t_first,
                                                                        uint32_t generations)
 {
+    static_assert(LT >= 8 && LT <= 64 && (LT & (LT - 1)) == 0, "lane count");
     __shared__ f4 s_row[2][kResidentMaxWaves][64];
     __shared__ unsigned long long s_key[2][kResidentMaxWaves];
     __shared__ uint32_t s_cnt[2];  // improved pBests of the generation (LDS atomics)
 
-    const uint32_t L = S.lanes;
-    const uint32_t lsh = (uint32_t)__builtin_ctz(L);
+    constexpr uint32_t L = LT;
+    constexpr uint32_t lsh = (uint32_t)__builtin_ctz(L);
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t nwaves = blockDim.x >> 6;
     const uint32_t ln = threadIdx.x & (L - 1u);
@@ -269,15 +272,29 @@ __global__ __launch_bounds__(kResidentMaxThreads) void k_resident_paper(SwarmDev
     }
 }
 
+template <int KIND, bool EQ21, int LT>
+static void launch_paper_lanes(const SwarmDev &S, uint32_t slots, uint32_t t_first, uint32_t gens,
+                               dim3 block, hipStream_t st)
+{
+    switch (slots) {
+    case 1: hipLaunchKernelGGL((k_resident_paper<KIND, EQ21, 1, LT>), dim3(1), block, 0, st, S, t_first, gens); break;
+    case 2: hipLaunchKernelGGL((k_resident_paper<KIND, EQ21, 2, LT>), dim3(1), block, 0, st, S, t_first, gens); break;
+    case 3: hipLaunchKernelGGL((k_resident_paper<KIND, EQ21, 3, LT>), dim3(1), block, 0, st, S, t_first, gens); break;
+    default: hipLaunchKernelGGL((k_resident_paper<KIND, EQ21, 4, LT>), dim3(1), block, 0, st, S, t_first, gens); break;
+    }
+}
+
+// S.lanes is the STREAM engine's FP32 lane count, a power of two in [8, 64]
+// (checked by the caller).
 template <int KIND, bool EQ21>
 static void launch_paper_slots(const SwarmDev &S, uint32_t slots, uint32_t t_first, uint32_t gens,
                                dim3 block, hipStream_t st)
 {
-    switch (slots) {
-    case 1: hipLaunchKernelGGL((k_resident_paper<KIND, EQ21, 1>), dim3(1), block, 0, st, S, t_first, gens); break;
-    case 2: hipLaunchKernelGGL((k_resident_paper<KIND, EQ21, 2>), dim3(1), block, 0, st, S, t_first, gens); break;
-    case 3: hipLaunchKernelGGL((k_resident_paper<KIND, EQ21, 3>), dim3(1), block, 0, st, S, t_first, gens); break;
-    default: hipLaunchKernelGGL((k_resident_paper<KIND, EQ21, 4>), dim3(1), block, 0, st, S, t_first, gens); break;
+    switch (S.lanes) {
+    case 8: launch_paper_lanes<KIND, EQ21, 8>(S, slots, t_first, gens, block, st); break;
+    case 16: launch_paper_lanes<KIND, EQ21, 16>(S, slots, t_first, gens, block, st); break;
+    case 32: launch_paper_lanes<KIND, EQ21, 32>(S, slots, t_first, gens, block, st); break;
+    default: launch_paper_lanes<KIND, EQ21, 64>(S, slots, t_first, gens, block, st); break;
     }
 }
 
@@ -476,7 +493,8 @@ int launch_resident(const SwarmDev &S, uint32_t t_first, uint32_t generations, v
     if (is_paper_kind(S.kind)) {
         // The lanes must be the STREAM engine's FP32 count (the context sets
         // them so); the gBest row is staged in 64 chunks of LDS at most.
-        if (S.lanes != host::stream_lanes(S.d, STORE_F32) || S.storage != STORE_F32 || S.chunks > 64u)
+        if (S.lanes != host::stream_lanes(S.d, STORE_F32) || S.storage != STORE_F32 || S.chunks > 64u ||
+            (S.lanes != 8u && S.lanes != 16u && S.lanes != 32u && S.lanes != 64u))
             return (int)hipErrorInvalidValue;
         // One particle per group when they all fit; otherwise the full
         // workgroup, so that particle i sits in group i mod G of slot i / G:

@@ -28,7 +28,7 @@ uint32_t stream_lanes(uint32_t d, int storage);
 uint32_t resident_paper_slots(uint32_t n, uint32_t d);
 // Per function f1..f9, the most waves of particles per SIMD (n times lanes
 // per particle over 256) for which AUTO picks the one-workgroup engine.
-constexpr uint32_t kResidentPaperAutoWaves[9] = {16, 15, 11, 15, 11, 7, 8, 15, 8};
+constexpr uint32_t kResidentPaperAutoWaves[9] = {16, 16, 14, 15, 11, 8, 10, 16, 9};
 uint32_t round_up(uint32_t x, uint32_t m);
 // ceil(c 2^32) for c in [0, 1] (exact: the product by 2^32 is exact).
 uint64_t threshold(double c);

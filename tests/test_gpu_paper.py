@@ -159,10 +159,10 @@ def test_resident_single_launch_against_oracle():
                                            ("f4", 240, 50, ("resident", "f32", 16)),
                                            ("f4", 241, 50, ("stream", "u24", 16)),
                                            ("f4", 350, 50, ("stream", "u24", 16)),
-                                           ("f6", 112, 50, ("resident", "f32", 16)),
-                                           ("f6", 113, 50, ("stream", "u24", 16)),
-                                           ("f3", 176, 50, ("resident", "f32", 16)),
-                                           ("f3", 177, 50, ("stream", "u24", 16)),
+                                           ("f6", 128, 50, ("resident", "f32", 16)),
+                                           ("f6", 129, 50, ("stream", "u24", 16)),
+                                           ("f3", 224, 50, ("resident", "f32", 16)),
+                                           ("f3", 225, 50, ("stream", "u24", 16)),
                                            ("f5", 177, 50, ("stream", "u24", 16)),
                                            ("f1", 30, 130, ("resident", "f32", 64)),
                                            ("sphere", 100, 30, ("resident", "f32", 8)),
@@ -170,7 +170,7 @@ def test_resident_single_launch_against_oracle():
 def test_auto_engine_choice(kind, n, d, want):
     """AUTO takes the one-workgroup engine for Table 3.2's functions up to
     a per-function number of waves of particles per SIMD (N L / 256: 15 for
-    f4, 7 for f6, 11 for f3, 11 for f5), STREAM beyond; the context reports
+    f4, 8 for f6, 14 for f3, 11 for f5), STREAM beyond; the context reports
     what it resolved to."""
     from paper_2110_01470_amd.binding import Swarm
 
